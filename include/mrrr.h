@@ -1,0 +1,199 @@
+/*
+ * mrrr.h -- C ABI of libmrrr, an MRRR (Multiple Relatively Robust
+ * Representations) eigensolver for real symmetric tridiagonal matrices on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem is the one the thesis states for its MRRR driver (Alg. 3.2 and
+ * Sec. 3.2.1): given the diagonal d (alpha_1..alpha_n) and off-diagonal e
+ * (beta_1..beta_{n-1}) of T, compute the eigenpairs (lambda_i, z_i) for all
+ * i, for the indices il..iu, or for the eigenvalues in the half-open value
+ * interval [vl, vu).  Eigenvalues are returned in ascending order; Z holds
+ * the matching orthonormal eigenvectors column by column (column-major).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers marked "device" are HIP device pointers; "host" ones are host
+ *    memory.  The caller owns every buffer it passes; the library never
+ *    modifies inputs and never frees caller memory.
+ *  - All GPU work is enqueued on the handle's stream (mrrr_set_stream); a call
+ *    returns after its work is enqueued and, where stated, after a
+ *    synchronisation needed to report host-side results.
+ *  - Return value: 0 on success; a positive mrrr_status_t on failure or
+ *    warning; -(k) when the k-th argument (1-based, handle = 1) is invalid.
+ *    Arguments are validated before anything is launched.
+ *  - Eigenvector sign: when opts->sign_convention is 1 (default), the entry
+ *    of largest magnitude of each vector is positive (ties: lowest index).
+ *  - One handle per host thread; calls on one handle must not overlap.
+ */
+#ifndef MRRR_H
+#define MRRR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrrr_handle_s *mrrr_handle_t;
+typedef struct mrrr_batched_plan_s *mrrr_batched_plan_t;
+
+/* Status codes (positive).  Negative returns name an invalid argument. */
+typedef enum {
+    MRRR_OK = 0,
+    /* A new representation was accepted although its element growth was
+     * above the threshold (Alg. 3.8, last line: "return the one with the
+     * smallest element growth"), or a cluster hit the depth limit.  Outputs
+     * are filled; stats->n_unverified_rrr says how often.  "Code may fail but
+     * should never lie" (Sec. 3.2.3). */
+    MRRR_WARN_UNVERIFIED = 1,
+    MRRR_ENOMEM = 2,     /* device allocation or a work-queue capacity failed */
+    MRRR_ENOCONV = 3,    /* an eigenvalue failed to converge */
+    MRRR_EHIP = 4,       /* a HIP runtime call failed */
+    MRRR_ENOTIMPL = 5,   /* a valid but unsupported request */
+    MRRR_ETIMEOUT = 6,   /* the device watchdog stopped the solve */
+    MRRR_EINTERNAL = 7   /* an internal consistency check failed */
+} mrrr_status_t;
+
+typedef enum {
+    MRRR_RANGE_ALL = 0,    /* all n eigenpairs */
+    MRRR_RANGE_VALUE = 1,  /* eigenvalues in [vl, vu) (Sec. 3.2.1) */
+    MRRR_RANGE_INDEX = 2   /* eigenvalues il..iu, 1-based (Sec. 3.2.1) */
+} mrrr_range_t;
+
+/* Tunables.  Defaults from mrrr_default_options follow the thesis. */
+typedef struct {
+    int32_t jobz;            /* 0: eigenvalues only; 1: eigenvalues and vectors */
+    int32_t sign_convention; /* 1: largest-magnitude entry positive; 0: as computed */
+    double gaptol;           /* relative gap separating singletons, 1e-3 (Sec. 4.1.4) */
+    double rtol_class;       /* classification accuracy, 1e-2*gaptol (Sec. 3.2.2) */
+    double perturb_xi;       /* root perturbation bound in units of eps, 8 (Alg. 3.2) */
+    uint64_t seed;           /* seed of the root perturbation */
+    int32_t max_rqi;         /* Rayleigh-quotient steps before bisection, 10 */
+    int32_t max_shift_tries; /* shift candidates for a new RRR, 8 (Alg. 3.8) */
+    int32_t max_depth;       /* deepest representation tree allowed, 64 */
+    int32_t workers;         /* persistent-kernel wavefronts; 0 = fill the GPU */
+    int32_t slice_min;       /* smallest refinement slice (eigenvalues), 2 */
+    int32_t slice_max;       /* largest refinement slice (eigenvalues), 64 */
+    double timeout_s;        /* device watchdog for one solve, seconds (30) */
+    double arena_scale;      /* node-pool size factor (1.0); grows on ENOMEM */
+} mrrr_options_t;
+
+/* Per-call statistics (host struct, filled after the work completes). */
+typedef struct {
+    int64_t m;                 /* eigenpairs computed */
+    int64_t n_blocks;          /* irreducible blocks after splitting */
+    int64_t n_nodes;           /* representations: roots + clusters */
+    int64_t largest_cluster;   /* biggest cluster at any depth */
+    int32_t dmax;              /* depth of the representation tree */
+    int32_t pad;
+    int64_t n_unverified_rrr;  /* RRRs accepted without passing the test */
+    int64_t n_bisect_fallback; /* singletons that fell back to bisection */
+    int64_t n_nan_retry;       /* recurrences redone after a NaN */
+    int64_t qd_steps;          /* lane-steps of the qd / Sturm recurrences */
+    int64_t n_tasks;           /* device tasks executed */
+    int64_t n_singleton_tasks; /* singleton bundles executed */
+    int64_t n_rqi_iters;       /* lane Rayleigh-quotient iterations */
+    int64_t arena_bytes;       /* node-pool bytes used */
+    double ms;                 /* device time of the solve (hipEvent), ms */
+} mrrr_stats_t;
+
+/* Creates a handle on HIP device `device`.  The handle owns a workspace that
+ * grows on demand and is released by mrrr_destroy.  Errors: -1 (h NULL),
+ * -2 (bad device), MRRR_EHIP. */
+int mrrr_create(mrrr_handle_t *h, int device);
+
+/* Releases the handle and its workspace (synchronises its stream first). */
+int mrrr_destroy(mrrr_handle_t h);
+
+/* Sets the stream (a hipStream_t; NULL = the legacy default stream) on which
+ * all later work of this handle is enqueued. */
+int mrrr_set_stream(mrrr_handle_t h, void *stream);
+
+/* Fills *o with the defaults. */
+void mrrr_default_options(mrrr_options_t *o);
+
+/* Human-readable text for a status code (static storage). */
+const char *mrrr_status_string(int status);
+
+/* mrrr_dstemr: eigenpairs of T = tridiag(e, d, e) (Alg. 3.2 on each block
+ * left by the splitting of Sec. 3.2.1).
+ *   n        matrix order, n >= 0.
+ *   d        device, n doubles: diagonal alpha_1..alpha_n.
+ *   e        device, n-1 doubles: off-diagonal beta_1..beta_{n-1} (may be
+ *            NULL when n <= 1).
+ *   range    MRRR_RANGE_ALL / _VALUE ([vl, vu), vl < vu) / _INDEX
+ *            (1 <= il <= iu+1, iu <= n; il = iu+1 asks for nothing).
+ *   opts     host, may be NULL for the defaults.
+ *   m        host, out: number of eigenpairs found.  For ALL and INDEX it
+ *            is known without waiting; for VALUE the call synchronises.
+ *   w        device, >= m doubles, out: ascending eigenvalues.
+ *   Z        device, out (ignored when opts->jobz == 0): n x m column-major
+ *            with leading dimension ldz >= max(1, n).  For VALUE ranges size
+ *            Z for the largest possible m (e.g. n columns).
+ *   stats    host, may be NULL.  When non-NULL the call synchronises and
+ *            fills it.
+ * The call always waits for the device to finish (it must read back the
+ * device status word to honour "never lie").  Errors: negative argument
+ * index, MRRR_ENOMEM, MRRR_ETIMEOUT, MRRR_ENOTIMPL (INDEX range on a matrix
+ * that splits into several blocks), MRRR_EHIP.  MRRR_WARN_UNVERIFIED still
+ * fills all outputs. */
+int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double *d, const double *e,
+                int range, double vl, double vu, int64_t il, int64_t iu,
+                const mrrr_options_t *opts, int64_t *m, double *w, double *Z,
+                int64_t ldz, mrrr_stats_t *stats);
+
+/* Batched form: all eigenpairs of `batch` independent tridiagonals, solved
+ * by one persistent launch (no counterpart in the thesis; tridiagonals from
+ * many Lanczos runs are the motivating case of Sec. 2.4).
+ *   n_offsets host, batch+1 int64: matrix b occupies rows
+ *             [n_offsets[b], n_offsets[b+1]) of d_cat and e_cat.
+ *   d_cat     device, n_offsets[batch] doubles.
+ *   e_cat     device, n_offsets[batch] doubles; e_cat[n_offsets[b]+i] is
+ *             beta_{i+1} of matrix b for i < n_b - 1; the last slot of each
+ *             matrix is padding and is ignored.
+ *   w_cat     device, out: n_offsets[batch] doubles, matrix b's eigenvalues
+ *             ascending at [n_offsets[b], n_offsets[b+1]).
+ *   Z_cat     device, out: matrix b's n_b x n_b eigenvector matrix
+ *             (column-major, ld n_b) starts at z_offsets[b] (host int64 array
+ *             of batch entries; NULL means packed: sum over c < b of n_c^2).
+ * The first call with a given (batch, sizes, options) builds a plan and
+ * captures the launch sequence in a hipGraph; later calls replay it. */
+int mrrr_dstemr_batched(mrrr_handle_t h, int64_t batch, const int64_t *n_offsets,
+                        const double *d_cat, const double *e_cat,
+                        const int64_t *z_offsets, const mrrr_options_t *opts,
+                        double *w_cat, double *Z_cat, mrrr_stats_t *stats);
+
+/* Reverse-mode derivative of a loss L(w, Z) through the eigendecomposition
+ * of T = tridiag(e, d, e) (all n eigenpairs, as returned by mrrr_dstemr).
+ *   w, Z       device: eigenvalues (n) and eigenvectors (n x n, ld ldz).
+ *   wbar       device, n doubles: dL/dw (NULL = zero).
+ *   Zbar       device, n x n (ld ldzbar): dL/dZ (NULL = zero).
+ *   gap_mask_rel  pairs with |w_b - w_a| < gap_mask_rel*||T|| (||T|| =
+ *              max|w|) are left out of the eigenvector term and counted.
+ *   dbar       device, out, n doubles: dL/dd_j = (Z M Z^T)_jj.
+ *   ebar       device, out, n-1 doubles: dL/de_j = (ZMZ^T)_{j,j+1} +
+ *              (ZMZ^T)_{j+1,j}, with M = diag(wbar) + F o (Z^T Zbar),
+ *              F_ab = 1/(w_b - w_a) off the diagonal.
+ *   n_masked   host, out, may be NULL: number of masked (a, b) pairs; the call
+ *              synchronises when it is non-NULL.
+ * The two products with Z run on FP64 matrix cores. */
+int mrrr_dstemr_backward(mrrr_handle_t h, int64_t n, const double *w,
+                         const double *Z, int64_t ldz, const double *wbar,
+                         const double *Zbar, int64_t ldzbar, double gap_mask_rel,
+                         double *dbar, double *ebar, int64_t *n_masked);
+
+/* Batched backward over the layout of mrrr_dstemr_batched: w_cat, wbar_cat,
+ * dbar_cat and ebar_cat use n_offsets (ebar keeps one pad slot per matrix,
+ * written as 0); Z_cat and Zbar_cat use z_offsets (NULL = packed).  wbar_cat
+ * or Zbar_cat may be NULL. */
+int mrrr_dstemr_backward_batched(mrrr_handle_t h, int64_t batch,
+                                 const int64_t *n_offsets, const double *w_cat,
+                                 const double *Z_cat, const int64_t *z_offsets,
+                                 const double *wbar_cat, const double *Zbar_cat,
+                                 double gap_mask_rel, double *dbar_cat,
+                                 double *ebar_cat, int64_t *n_masked);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRRR_H */

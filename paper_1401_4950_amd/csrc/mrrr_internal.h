@@ -1,0 +1,138 @@
+// Internal data layout shared by the host runtime and the gfx950 kernels.
+//
+// One solve works on P "problems" (1 for mrrr_dstemr, B for the batched
+// form).  Each problem is split into irreducible blocks (Sec. 3.2.1); each
+// block gets a root representation and a tree of cluster representations
+// (the representation tree of Sec. 3.1.2), processed as device tasks drawn
+// from three queues (Sec. 4.1: refinement > cluster > singleton priority).
+//
+// Indexing: every eigenvalue of every block owns one "slot", its global row
+// index row0(block) + j - 1 for the block-local index j (1-based).  Slots
+// index the bracket arrays lo/hi/gap and the checkpoint rows.
+#pragma once
+
+#include <stdint.h>
+
+namespace mrrr {
+
+constexpr int kWave = 64;      // wavefront = one worker
+constexpr int kTile = 64;      // rows of a representation staged in LDS at once
+constexpr int kCkb = 16;       // rows between checkpoints of the twisted solver
+constexpr int kNumQ = 3;       // 0: refine, 1: root + cluster, 2: singleton
+constexpr int kQRefine = 0, kQCluster = 1, kQSingle = 2;
+
+enum TaskType : int32_t {
+    kTaskRoot = 1,     // build the root RRR of a block and start its refinement
+    kTaskRefine = 2,   // refine a slice of one node's eigenvalue brackets
+    kTaskCluster = 3,  // new RRR for a cluster (Alg. 3.8), then refine its members
+    kTaskSingle = 4    // bundle of singletons of one node (Alg. 4.3 + Alg. 3.7)
+};
+
+enum RefineMode : int32_t { kModeClass = 0, kModeFull = 1 };
+
+enum ErrCode : int32_t {
+    kErrNone = 0, kErrNoMem = 2, kErrNoConv = 3, kErrNotImpl = 5,
+    kErrTimeout = 6, kErrInternal = 7,
+    kErrBadD = 100, kErrBadE = 101   // non-finite input data
+};
+
+struct Task {
+    int32_t type;
+    int32_t node;   // node id (root: block id)
+    int32_t a;      // first member (local index) or singleton-list offset
+    int32_t b;      // last member (inclusive) or count; refine: mode in bit 30
+};
+
+struct Problem {
+    int64_t row0;     // first row in d/e and first slot
+    int64_t n;
+    int64_t zoff;     // element offset of this problem's Z block
+    int64_t ldz;
+    int64_t woff;     // element offset of this problem's w
+    int64_t il, iu;   // requested indices (INDEX range)
+    double vl, vu;    // requested values (VALUE range)
+    int32_t range;
+    int32_t nblocks;  // device: number of irreducible blocks
+    int64_t m;        // device: number of eigenpairs returned
+    double bnorm;     // device: Gershgorin bound of the whole problem
+    int64_t ck_base;  // checkpoint region (doubles) of this problem
+    int64_t ck_slot0; // first slot with a checkpoint column
+    int64_t ck_stride;
+    int32_t flags;    // device: bit0 = several blocks (final merge needed)
+    int32_t pad;
+};
+
+struct Block {
+    int32_t prob;
+    int32_t root;     // node id of the root representation (-1 = none)
+    int64_t row0;     // global first row
+    int64_t n;
+    int64_t k0, k1;   // working local indices (wanted plus one guard each side)
+    int64_t w0, w1;   // wanted local indices, 1-based inclusive
+    int64_t col0;     // output column of local index w0 within the problem
+};
+
+struct Node {
+    int64_t data;     // arena offset: D at data, L at data+n (N-representation)
+    int32_t block;
+    int32_t depth;
+    int32_t a, b;     // member local indices, inclusive
+    int32_t parent;
+    int32_t pending;  // refinement slices still running
+    double sigma;     // accumulated shift: lambda(T) = sigma + lambda(node)
+    double lgap, rgap;  // absolute gaps to the neighbours outside [a, b]
+    double spdiam;    // spectral diameter of the block's root
+    double pad;
+};
+
+struct Ctl {
+    uint64_t head[kNumQ];
+    uint64_t pad0[8 - kNumQ];
+    uint64_t tail[kNumQ];
+    uint64_t pad1[8 - kNumQ];
+    int64_t pending;      // tasks pushed and not yet finished
+    int32_t error;        // first error code raised on the device
+    int32_t dmax;
+    uint64_t arena_top;   // doubles handed out from the node arena
+    int32_t node_top;
+    int32_t pad2;
+    int64_t slist_top;
+    int64_t n_nodes, largest_cluster, n_unverified, n_fallback, n_nan;
+    int64_t qd_steps, n_tasks, n_single, n_rqi, n_blocks;
+};
+
+struct Params {
+    const double* d;
+    const double* e;
+    double* w;
+    double* Z;
+    Problem* probs;
+    int32_t nprob;
+    int32_t jobz;
+    Block* blocks;        // problem p's blocks live at blocks[row0(p) + b]
+    Node* nodes;
+    int32_t max_nodes;
+    int32_t nworkers;
+    Task* q[kNumQ];
+    uint64_t* seq[kNumQ];
+    uint64_t qcap[kNumQ];
+    double* lo;           // per slot bracket, in the frame of its current node
+    double* hi;
+    double* gap;          // per slot absolute gap (singletons)
+    uint8_t* vflag;       // per slot: bit0 lo verified, bit1 hi verified
+    int32_t* slist;       // singleton lists
+    int64_t slist_cap;
+    double* arena;
+    uint64_t arena_cap;   // doubles
+    double* ck;           // checkpoints of the twisted solver
+    double* colbuf;       // one column per problem (final merge)
+    int32_t* perm;        // per slot scratch for the final merge
+    Ctl* ctl;
+    int64_t total_rows;
+    double gaptol, rtol, xi;
+    uint64_t seed;
+    int32_t max_rqi, max_tries, max_depth, slice_min, slice_max, sign_conv;
+    uint64_t timeout_ticks;
+};
+
+}  // namespace mrrr

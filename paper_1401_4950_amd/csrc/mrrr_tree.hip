@@ -1,0 +1,1650 @@
+// MRRR for symmetric tridiagonal matrices on gfx950: the device side.
+//
+// One wavefront (64 lanes, one workgroup) is one worker.  Workers drain three
+// device-side task queues in priority order refine > root/cluster >
+// singleton (the R > C > S order of the thesis' task-based MRRR, Sec. 4.1,
+// Algs. 4.1-4.3).  Every sweep over a representation stages the rows in LDS
+// (D, and the derived D*L and D*L*L of Sec. 4.1.3) so that all 64 lanes read
+// the same row from one broadcast; the lanes carry different shifts
+// (multisection) or different eigenvalues (singleton bundles).
+//
+// Numerical kernels, all in FP64:
+//   negcount_rep   NegCount on L D L^T (App. B, Alg. B.2): the sign count of
+//                  the stationary qd transform.
+//   negcount_T     NegCount on T (App. B, Alg. B.1), for the root.
+//   dstqds         L+ D+ L+^T = L D L^T - tau I (Alg. 3.5), for new RRRs.
+//   twisted        dstqds + the progressive transform (Alg. 3.6) + gamma_k
+//                  and the twist index r = argmin |gamma_k| (Alg. 3.7), with
+//                  the norm of the solution of N_r^T z = e_r accumulated as
+//                  nested sums so that no O(n) per-lane scratch is needed:
+//                  the forward pass keeps (s, h) every 16 rows, the backward
+//                  pass recomputes each 16-row block in registers.
+//   solve_vector   N_r^T z = e_r (Alg. 3.7, lower half) from the same
+//                  checkpoints, written straight into Z, normalised.
+#include <hip/hip_runtime.h>
+
+#include "mrrr_internal.h"
+
+namespace mrrr {
+
+#define DEV __device__ __forceinline__
+
+constexpr double kEps = 0x1p-53;               // unit roundoff
+constexpr double kSafmin = 2.2250738585072014e-308;
+constexpr int kMaxPass = 400;
+
+// ---------------------------------------------------------------- helpers
+
+DEV int lane_id() { return (int)threadIdx.x; }
+
+// IEEE sign bit, so that -0 counts as negative (App. B, remark on SignBit).
+DEV int sbit(double x) { return (int)((unsigned long long)__double_as_longlong(x) >> 63); }
+
+// The guarded quotient of Algs. 3.5, 3.6 and B.2: q := 1 when both numerator
+// and denominator are infinite, else num / den.
+DEV double qd_q(double num, double den) {
+    return (__builtin_isinf(num) && __builtin_isinf(den)) ? 1.0 : num / den;
+}
+
+DEV uint64_t ld_acq64(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void st_rel64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV int64_t ld_rlx_i64(int64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV int32_t ld_rlx_i32(int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Brackets of other workers' eigenvalues are read and written with relaxed
+// agent-scope atomics (a stale value is a wider, still valid bracket).
+DEV double ld_rlx_d(double* p) {
+    unsigned long long v = __hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)v);
+}
+DEV void st_rlx_d(double* p, double x) {
+    __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(x),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+DEV void set_error(const Params& P, int code) {
+    if (lane_id() == 0) {
+        int32_t expect = 0;
+        __hip_atomic_compare_exchange_strong(&P.ctl->error, &expect, code, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+DEV void add_stat(int64_t* p, int64_t v) {
+    if (lane_id() == 0 && v != 0)
+        __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+DEV double wave_min(double x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+    return x;
+}
+DEV double wave_max(double x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    return x;
+}
+DEV int wave_or(int x) {
+    return __ballot(x != 0) != 0ull;
+}
+
+// splitmix64 (Steele, Lea and Flood, 2014): a counter-based generator for the
+// "random" relative perturbation of the root (Alg. 3.2, line 2).
+DEV uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+DEV double unit_pm1(uint64_t seed, uint64_t idx) {
+    uint64_t h = splitmix64(seed ^ splitmix64(idx));
+    return ((double)(h >> 11) * 0x1p-53) * 2.0 - 1.0;
+}
+
+// ---------------------------------------------------------------- LDS
+
+struct Shared {
+    double ta[kTile], tb[kTile], tc[kTile];   // staged rows
+    double m_lo[kWave], m_hi[kWave];          // multisection members
+    double m_sig[kWave];
+    int64_t m_slot[kWave];
+    int32_t m_j[kWave];
+    int32_t m_flag[kWave];                    // bit0 lo verified, bit1 hi verified
+    int32_t m_cnt[kWave];
+    int32_t ulist[kWave];
+    Task task;
+    int32_t ibc[8];
+    double dbc[8];
+};
+
+// Rows [base, base + 64) of an N-representation (D, L): stage D, D*L and
+// D*L*L (the derived data that all lanes share).
+DEV void load_rep_tile(Shared& S, const double* D, const double* L, int64_t base, int64_t n) {
+    const int l = lane_id();
+    const int64_t r = base + l;
+    double dv = 0.0, dl = 0.0, dll = 0.0;
+    if (r < n) {
+        dv = D[r];
+        if (r < n - 1) {
+            const double lv = L[r];
+            dl = dv * lv;
+            dll = dl * lv;
+        }
+    }
+    __syncthreads();
+    S.ta[l] = dv;
+    S.tb[l] = dl;
+    S.tc[l] = dll;
+    __syncthreads();
+}
+
+// Rows of T: alpha_i in ta, beta_{i-1}^2 in tb (row i couples to row i-1).
+DEV void load_T_tile(Shared& S, const double* d, const double* e, int64_t base, int64_t n) {
+    const int l = lane_id();
+    const int64_t r = base + l;
+    double a = 0.0, b2 = 0.0, b = 0.0;
+    if (r < n) {
+        a = d[r];
+        if (r >= 1) {
+            b = e[r - 1];
+            b2 = b * b;
+        }
+    }
+    __syncthreads();
+    S.ta[l] = a;
+    S.tb[l] = b2;
+    S.tc[l] = b;
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ Sturm counts
+
+// NegCount(L D L^T, sigma) for one shift per lane (App. B, Alg. B.2).
+DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, double sigma) {
+    double s = -sigma;
+    int cnt = 0;
+    for (int64_t base = 0; base < n; base += kTile) {
+        load_rep_tile(S, D, L, base, n);
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        if (lim == kTile) {
+#pragma unroll 8
+            for (int t = 0; t < kTile; ++t) {
+                const double dp = s + S.ta[t];
+                cnt += sbit(dp);
+                s = qd_q(s, dp) * S.tc[t] - sigma;
+            }
+        } else {
+            for (int t = 0; t < lim; ++t) {
+                const double dp = s + S.ta[t];
+                cnt += sbit(dp);
+                s = qd_q(s, dp) * S.tc[t] - sigma;
+            }
+        }
+    }
+    return cnt;
+}
+
+// NegCount(T, sigma) for one shift per lane (App. B, Alg. B.1), IEEE form:
+// a zero pivot turns the next one into -inf and the count stays right.
+DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, double sigma) {
+    double piv = 1.0;
+    int cnt = 0;
+    for (int64_t base = 0; base < n; base += kTile) {
+        load_T_tile(S, d, e, base, n);
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        for (int t = 0; t < lim; ++t) {
+            const int64_t i = base + t;
+            piv = (i == 0) ? (S.ta[t] - sigma) : ((S.ta[t] - sigma) - S.tb[t] / piv);
+            cnt += sbit(piv);
+        }
+    }
+    return cnt;
+}
+
+// ----------------------------------------------------- multisection engine
+//
+// Refines the brackets [lo, hi] of up to 64 eigenvalues of one
+// representation (members m = 0..M-1 in S.m_*).  Each pass gives every
+// unconverged member L = 64 / (#unconverged) lanes (a power of two), each
+// lane counting at one interior point; the bracket shrinks to the two
+// neighbouring points whose counts straddle the index (Alg. 3.3 with L
+// points instead of one).  Bracket ends that were never confirmed by a count
+// are checked before a member is declared converged; a failed check widens
+// the bracket (as an implementation of Alg. 3.3 must, Sec. 3.2.2).
+struct MemberCtx {
+    int mode;            // kModeClass: rtol_class, kModeFull: full accuracy
+    int32_t na, nb;      // member range of the node (neighbour tests)
+    int64_t slot_base;   // slot = slot_base + j
+    bool publish;        // write brackets to global memory after every pass
+};
+
+DEV double dist0(double a, double b) {   // distance of [a, b] from zero
+    return a > 0.0 ? a : (b < 0.0 ? -b : 0.0);
+}
+
+// True when reldist(j, j+1) < gaptol for every refinement of the current
+// brackets (Sec. 3.2.3 classification): then j and j+1 end up in one cluster
+// whatever more bisection does.
+DEV bool surely_clustered(double lo1, double hi1, double lo2, double hi2, double gaptol) {
+    const double num = hi2 - lo1;
+    const double den = fmax(dist0(lo1, hi1), dist0(lo2, hi2));
+    return num < gaptol * den;
+}
+
+DEV bool bracket_done(const Params& P, int mode, double lo, double hi) {
+    const double w = hi - lo;
+    const double mx = fmax(fabs(lo), fabs(hi));
+    const double mid = lo + 0.5 * w;
+    if (!(mid > lo && mid < hi)) return true;          // no double strictly inside
+    if (mode == kModeFull) return (w <= 2.0 * kEps * mx) || (w <= 2.0 * kSafmin);
+    return w <= fmax(P.rtol * mx, 2.0 * kSafmin);       // Alg. 3.3 stopping rule
+}
+
+DEV void refine_members(Shared& S, const Params& P, const double* D, const double* L, int64_t n,
+                        int M, const MemberCtx& C, int64_t& steps) {
+    const int l = lane_id();
+    // a joint first pass when all members share one bracket (a fresh root):
+    // 64 points spread over the common interval place every member at once
+    bool joint = M > 1;
+    if (joint) {
+        int same = 1;
+        if (l < M) same = (S.m_lo[l] == S.m_lo[0] && S.m_hi[l] == S.m_hi[0]) ? 1 : 0;
+        joint = __ballot(same == 0) == 0ull;
+    }
+    if (joint) {
+        const double lo = S.m_lo[0], hi = S.m_hi[0];
+        const double sig = lo + (hi - lo) * (double)(l + 1) / (double)(kWave + 1);
+        const int c = negcount_rep(S, D, L, n, sig);
+        steps += (int64_t)n * kWave;
+        __syncthreads();
+        S.m_cnt[l] = c;
+        S.m_sig[l] = sig;
+        __syncthreads();
+        if (l < M) {
+            const int j = S.m_j[l];
+            int a = 0, b = kWave;   // first sample whose count reaches j
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (S.m_cnt[mid] >= j) b = mid; else a = mid + 1;
+            }
+            // only points with a confirmed count become bracket ends
+            if (a < kWave && S.m_cnt[a] >= j) { S.m_hi[l] = S.m_sig[a]; S.m_flag[l] |= 2; }
+            if (a > 0 && S.m_cnt[a - 1] < j) { S.m_lo[l] = S.m_sig[a - 1]; S.m_flag[l] |= 1; }
+        }
+        __syncthreads();
+    }
+    for (int pass = 0; pass < kMaxPass; ++pass) {
+        // need: 0 done, 1 bisect the interior, 2 confirm an unverified end
+        int need = 0;
+        if (l < M) {
+            const double lo = S.m_lo[l], hi = S.m_hi[l];
+            bool conv = bracket_done(P, C.mode, lo, hi);
+            if (!conv && C.mode == kModeClass && C.na >= 0) {
+                const int j = S.m_j[l];
+                if (j > C.na && j < C.nb) {
+                    const int64_t sl = C.slot_base + j;
+                    const double llo = ld_rlx_d(P.lo + sl - 1), lhi = ld_rlx_d(P.hi + sl - 1);
+                    const double rlo = ld_rlx_d(P.lo + sl + 1), rhi = ld_rlx_d(P.hi + sl + 1);
+                    conv = surely_clustered(llo, lhi, lo, hi, P.gaptol) &&
+                           surely_clustered(lo, hi, rlo, rhi, P.gaptol);
+                }
+            }
+            need = !conv ? 1 : ((S.m_flag[l] & 3) != 3 ? 2 : 0);
+            S.m_cnt[l] = need;
+        }
+        const uint64_t um = __ballot(need != 0);
+        const int nu = __popcll(um);
+        if (nu == 0) break;
+        if (need != 0) S.ulist[__popcll(um & ((1ull << l) - 1ull))] = l;
+        __syncthreads();
+        int Lg = 1;
+        while (Lg * 2 * nu <= kWave) Lg *= 2;
+        const int u = l / Lg;
+        const int t = l % Lg;
+        const bool valid = (u < nu);
+        const int m = valid ? S.ulist[u] : 0;
+        const double lo = S.m_lo[m], hi = S.m_hi[m];
+        const int j = S.m_j[m];
+        const int fm = S.m_flag[m];
+        const int needm = S.m_cnt[m];
+        const double w = hi - lo;
+        int role = 0;        // 0 interior point, 1 confirm lo, 2 confirm hi
+        double sig;
+        if (needm == 2) {
+            const bool vlo = !(fm & 1), vhi = !(fm & 2);
+            if (vlo && vhi) role = (Lg >= 2 && (t & 1)) ? 2 : 1;
+            else role = vlo ? 1 : 2;
+            sig = (role == 1) ? lo : hi;
+        } else {
+            sig = lo + w * (double)(t + 1) / (double)(Lg + 1);
+        }
+        if (!valid) sig = 0.0;
+        const int c = negcount_rep(S, D, L, n, sig);
+        steps += (int64_t)n * (int64_t)__popcll(__ballot(valid));
+        // interior points: the first one of the group whose count reaches j
+        const int gb = u * Lg;
+        const uint64_t gmask = (Lg == 64) ? ~0ull : (((1ull << Lg) - 1ull) << (gb & 63));
+        const uint64_t ge = __ballot(valid && role == 0 && c >= j) & gmask;
+        const int tstar = ge ? (__ffsll((unsigned long long)ge) - 1 - gb) : Lg;
+        const double s_hi = __shfl(sig, gb + (tstar < Lg ? tstar : Lg - 1));
+        const double s_lo = __shfl(sig, gb + (tstar > 0 ? tstar - 1 : 0));
+        const uint64_t lo_good = __ballot(valid && role == 1 && c < j) & gmask;
+        const uint64_t lo_bad = __ballot(valid && role == 1 && c >= j) & gmask;
+        const uint64_t hi_good = __ballot(valid && role == 2 && c >= j) & gmask;
+        const uint64_t hi_bad = __ballot(valid && role == 2 && c < j) & gmask;
+        __syncthreads();
+        if (valid && t == 0) {
+            double nlo = lo, nhi = hi;
+            int nf = fm;
+            if (needm != 2) {
+                if (tstar < Lg) { nhi = s_hi; nf |= 2; }
+                if (tstar > 0) { nlo = s_lo; nf |= 1; }
+            } else {
+                const double mx = fmax(fabs(lo), fabs(hi));
+                const double wid = fmax(fmax(w, 4.0 * kEps * mx), 4.0 * kSafmin);
+                if (lo_good) nf |= 1;
+                if (hi_good) nf |= 2;
+                if (lo_bad) { nlo = lo - wid; nhi = lo; nf = (nf & ~1) | 2; }
+                else if (hi_bad) { nhi = hi + wid; nlo = hi; nf = (nf & ~2) | 1; }
+            }
+            S.m_lo[m] = nlo;
+            S.m_hi[m] = nhi;
+            S.m_flag[m] = nf;
+        }
+        __syncthreads();
+        if (C.publish && l < M) {
+            st_rlx_d(P.lo + S.m_slot[l], S.m_lo[l]);
+            st_rlx_d(P.hi + S.m_slot[l], S.m_hi[l]);
+        }
+    }
+}
+
+// --------------------------------------------- twisted factorisation (RQI)
+//
+// Per lane: the twisted factorisations N_k Delta_k N_k^T = L D L^T - lam I of
+// Alg. 3.7 for its own lam.  Forward: the stationary transform (Alg. 3.5),
+// s_i and the running h_i = sum_{k<=i} z_k^2 of the solution with z_i = 1
+// (h_{i+1} = 1 + lplus_i^2 h_i), checkpointed every kCkb rows.  Backward: the
+// progressive transform (Alg. 3.6, read with omega^-(i+1) := p(i+1) +
+// d(i)l(i)^2 on its first line), g_i = 1 + uminus_i^2 g_{i+1}, and
+// gamma_i = s_i + d_i * p_{i+1}/omega_{i+1}; r = argmin |gamma_i| (lowest i on
+// ties).  Then ||z||^2 = h_r + g_r - 1 for the solution of N_r^T z = e_r.
+struct CkPtr {
+    double* base;       // this lane's column of the checkpoint region
+    int64_t stride;     // distance between checkpoint rows
+    DEV double& at(int64_t c, int k) const { return base[(c * 3 + k) * stride]; }
+};
+
+struct TwistOut {
+    int neg;       // NegCount(lam) = #negative d+
+    int r;         // twist index (0-based row)
+    double gam;    // gamma_r
+    double nrm2;   // ||z||^2 with z_r = 1
+};
+
+DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
+                     const CkPtr& ck, int64_t& steps) {
+    TwistOut o;
+    // ---- forward: dstqds with checkpoints of (s, h)
+    double s = -lam, h = 1.0, dplast = 0.0;
+    int cnt = 0;
+    for (int64_t base = 0; base < n; base += kTile) {
+        load_rep_tile(S, D, L, base, n);
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        for (int t = 0; t < lim; ++t) {
+            const int64_t i = base + t;
+            if ((i & (kCkb - 1)) == 0 && live) {
+                ck.at(i / kCkb, 0) = s;
+                ck.at(i / kCkb, 1) = h;
+            }
+            const double dp = s + S.ta[t];
+            cnt += sbit(dp);
+            const double q = qd_q(s, dp);
+            const double lp = S.tb[t] / dp;
+            h = 1.0 + (lp * lp) * h;
+            dplast = dp;
+            s = q * S.tc[t] - lam;
+        }
+    }
+    steps += n;
+    // ---- backward: dqds (progressive) with argmin |gamma|
+    const int64_t cl = (n - 1) / kCkb;
+    double p = D[n - 1] - lam;
+    double g = 1.0;
+    double best = fabs(dplast);
+    int r = (int)(n - 1);
+    double gam_r = dplast, g_r = 1.0;
+    if (live) ck.at(cl, 2) = p;
+    const int64_t last_tile = ((n - 1) / kTile) * kTile;
+    for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
+        load_rep_tile(S, D, L, tb, n);
+        const int64_t cfirst = tb / kCkb;
+        const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
+        for (int64_t c = clast; c >= cfirst; --c) {
+            const int64_t b0 = c * kCkb;
+            const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);   // rows [b0, b1)
+            if (b0 >= b1) continue;
+            if (c < cl && live) ck.at(c, 2) = p;      // p_{b1}
+            // recompute s_i for the block from the forward checkpoint
+            double sreg[kCkb];
+            double sr = live ? ck.at(c, 0) : 0.0;
+#pragma unroll
+            for (int t = 0; t < kCkb; ++t) {
+                sreg[t] = sr;
+                if (b0 + t < b1) {
+                    const int k = (int)(b0 + t - tb);
+                    const double dp = sr + S.ta[k];
+                    sr = qd_q(sr, dp) * S.tc[k] - lam;
+                }
+            }
+#pragma unroll
+            for (int t = kCkb - 1; t >= 0; --t) {
+                if (b0 + t < b1) {
+                    const int k = (int)(b0 + t - tb);
+                    const double om = p + S.tc[k];
+                    const double q = qd_q(p, om);
+                    const double um = S.tb[k] / om;
+                    const double gam = sreg[t] + S.ta[k] * q;
+                    p = q * S.ta[k] - lam;
+                    g = 1.0 + (um * um) * g;
+                    if (fabs(gam) <= best) {
+                        best = fabs(gam);
+                        r = (int)(b0 + t);
+                        gam_r = gam;
+                        g_r = g;
+                    }
+                }
+            }
+        }
+    }
+    steps += 2 * n;
+    // ---- h_r from the nearest forward checkpoint (<= kCkb - 1 rows)
+    double hr = 1.0;
+    if (live) {
+        const int64_t c = r / kCkb;
+        double sr = ck.at(c, 0);
+        hr = ck.at(c, 1);
+        for (int64_t i = c * kCkb; i < r; ++i) {
+            const double dv = D[i], lv = L[i];
+            const double dl = dv * lv, dll = dl * lv;
+            const double dp = sr + dv;
+            const double q = qd_q(sr, dp);
+            const double lp = dl / dp;
+            hr = 1.0 + (lp * lp) * hr;
+            sr = q * dll - lam;
+        }
+    }
+    o.neg = cnt;
+    o.r = r;
+    o.gam = gam_r;
+    o.nrm2 = hr + g_r - 1.0;
+    return o;
+}
+
+// Solve N_r^T z = e_r (Alg. 3.7): z_r = 1; z_{i+1} = -uminus_i z_i above r;
+// z_i = -lplus_i z_{i+1} below r; the zero-pivot rules of Alg. 3.7 where a
+// pivot vanished (an index outside the matrix gives 0).  uminus / lplus are
+// recomputed per 16-row block from the checkpoints of the accepted
+// factorisation.  Each value is scaled by `scale` and stored to zcol[row]
+// when `write`; sum of squares returned.
+DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, double lam,
+                        bool live, int r, double scale, const CkPtr& ck, double* zcol, bool write,
+                        int64_t& steps) {
+    double ss = live ? 1.0 : 0.0;
+    if (live && write) zcol[r] = scale;
+    // ---- upward: rows r+1 .. n-1
+    double zc = 1.0, zm1 = 0.0, zr1 = 0.0;   // z_i, z_{i-1}, saved z_{r+1}
+    for (int64_t tb = 0; tb < n; tb += kTile) {
+        load_rep_tile(S, D, L, tb, n);
+        const int64_t cfirst = tb / kCkb;
+        const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
+        for (int64_t c = cfirst; c <= clast; ++c) {
+            const int64_t b0 = c * kCkb;
+            const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
+            if (b0 >= b1) continue;
+            double ureg[kCkb];
+            double pr = live ? ck.at(c, 2) : 0.0;
+#pragma unroll
+            for (int t = kCkb - 1; t >= 0; --t) {
+                ureg[t] = 0.0;
+                if (b0 + t < b1) {
+                    const int k = (int)(b0 + t - tb);
+                    const double om = pr + S.tc[k];
+                    ureg[t] = (om != 0.0) ? S.tb[k] / om : __builtin_inf();
+                    pr = qd_q(pr, om) * S.ta[k] - lam;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kCkb; ++t) {
+                const int64_t i = b0 + t;
+                if (i < b1 && i >= r) {
+                    double zn;
+                    if (!__builtin_isinf(ureg[t])) {
+                        zn = -ureg[t] * zc;
+                    } else {
+                        // omega(i+1) = 0: z_{i+1} = -(d_{i-1} l_{i-1} / d_i l_i) z_{i-1}
+                        const int k = (int)(i - tb);
+                        zn = 0.0;
+                        if (i - 1 >= r && i >= 1) {
+                            const double dlm = D[i - 1] * L[i - 1];
+                            zn = -(dlm / S.tb[k]) * zm1;
+                        }
+                    }
+                    if (i == r) zr1 = zn;
+                    zm1 = zc;
+                    zc = zn;
+                    ss += zn * zn;
+                    if (live && write) zcol[i + 1] = zn * scale;
+                }
+            }
+        }
+    }
+    // ---- downward: rows r-1 .. 0
+    zc = 1.0;                // z_{i+1}
+    double zp2 = zr1;        // z_{i+2}
+    const int64_t last_tile = ((n - 1) / kTile) * kTile;
+    for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
+        load_rep_tile(S, D, L, tb, n);
+        const int64_t cfirst = tb / kCkb;
+        const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
+        for (int64_t c = clast; c >= cfirst; --c) {
+            const int64_t b0 = c * kCkb;
+            const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
+            if (b0 >= b1) continue;
+            double lreg[kCkb];
+            double sr = live ? ck.at(c, 0) : 0.0;
+#pragma unroll
+            for (int t = 0; t < kCkb; ++t) {
+                lreg[t] = 0.0;
+                if (b0 + t < b1) {
+                    const int k = (int)(b0 + t - tb);
+                    const double dp = sr + S.ta[k];
+                    lreg[t] = (dp != 0.0) ? S.tb[k] / dp : __builtin_inf();
+                    sr = qd_q(sr, dp) * S.tc[k] - lam;
+                }
+            }
+#pragma unroll
+            for (int t = kCkb - 1; t >= 0; --t) {
+                const int64_t i = b0 + t;
+                if (i < b1 && i < r) {
+                    double zn;
+                    if (!__builtin_isinf(lreg[t])) {
+                        zn = -lreg[t] * zc;
+                    } else {
+                        // d+(i) = 0: z_i = -(d_{i+1} l_{i+1} / d_i l_i) z_{i+2}
+                        const int k = (int)(i - tb);
+                        zn = 0.0;
+                        if (i + 1 <= n - 2) {
+                            const double dlp = D[i + 1] * L[i + 1];
+                            zn = -(dlp / S.tb[k]) * zp2;
+                        }
+                    }
+                    zp2 = zc;
+                    zc = zn;
+                    ss += zn * zn;
+                    if (live && write) zcol[i] = zn * scale;
+                }
+            }
+        }
+    }
+    steps += 2 * n;
+    return ss;
+}
+
+// ------------------------------------------------------------- queues
+//
+// Bounded multi-producer multi-consumer rings, one per priority class.  Each
+// cell carries a sequence number: pos when free for the producer of ticket
+// pos, pos + 1 when it holds that producer's task, pos + cap once consumed.
+
+DEV bool try_pop(const Params& P, int q, Task* out) {   // one lane
+    const uint64_t cap = P.qcap[q];
+    for (int spin = 0; spin < 64; ++spin) {
+        uint64_t pos = __hip_atomic_load(&P.ctl->head[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t cell = pos % cap;
+        const uint64_t sq = ld_acq64(&P.seq[q][cell]);
+        if (sq == pos + 1) {
+            if (__hip_atomic_compare_exchange_strong(&P.ctl->head[q], &pos, pos + 1, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                *out = P.q[q][cell];
+                st_rel64(&P.seq[q][cell], pos + cap);
+                return true;
+            }
+        } else if (sq < pos + 1) {
+            return false;   // nothing published at the head
+        }
+    }
+    return false;
+}
+
+// Lane 0 reserves `count` tickets; every lane fills some of the cells.
+template <class Gen>
+DEV bool push_batch(const Params& P, int q, int count, Gen gen) {
+    if (count <= 0) return true;
+    const int l = lane_id();
+    __threadfence();   // publish everything this wave wrote before the tasks
+    uint64_t first = 0;
+    if (l == 0) {
+        __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        first = __hip_atomic_fetch_add(&P.ctl->tail[q], (uint64_t)count, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    }
+    first = __shfl(first, 0);
+    const uint64_t cap = P.qcap[q];
+    bool ok = true;
+    for (int k = l; k < count; k += kWave) {
+        const uint64_t pos = first + (uint64_t)k;
+        const uint64_t cell = pos % cap;
+        // wait until the cell is free for this ticket (bounded)
+        int spin = 0;
+        while (ld_acq64(&P.seq[q][cell]) != pos) {
+            if (++spin > (1 << 22) || __hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (!ok) break;
+        P.q[q][cell] = gen(k);
+        st_rel64(&P.seq[q][cell], pos + 1);
+    }
+    if (__ballot(!ok) != 0ull) {
+        set_error(P, kErrNoMem);
+        return false;
+    }
+    return true;
+}
+
+DEV bool push_one(const Params& P, int q, Task t) {
+    return push_batch(P, q, 1, [&](int) { return t; });
+}
+
+// Refinement slices of members [a, b] of a node (R-tasks of Sec. 4.1.3): the
+// slice size follows the thesis' rule of thumb -- about twice as many slices
+// as workers -- clamped to [slice_min, slice_max] eigenvalues.
+DEV void push_slices(const Params& P, int node_id, int a, int b, int mode) {
+    const int64_t M = (int64_t)b - a + 1;
+    int64_t sz = (M + 2 * (int64_t)P.nworkers - 1) / (2 * (int64_t)P.nworkers);
+    if (sz < P.slice_min) sz = P.slice_min;
+    if (sz > P.slice_max) sz = P.slice_max;
+    const int ns = (int)((M + sz - 1) / sz);
+    if (lane_id() == 0)
+        __hip_atomic_store(&P.nodes[node_id].pending, ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    push_batch(P, kQRefine, ns, [&](int k) {
+        Task t;
+        t.type = kTaskRefine;
+        t.node = node_id;
+        t.a = a + (int)(k * sz);
+        const int64_t e = (int64_t)t.a + sz - 1;
+        t.b = (int)(e < b ? e : b) | (mode << 30);
+        return t;
+    });
+}
+
+DEV int new_node(const Params& P) {   // all lanes get the id
+    int id = 0;
+    if (lane_id() == 0)
+        id = __hip_atomic_fetch_add(&P.ctl->node_top, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    id = __shfl(id, 0);
+    if (id >= P.max_nodes) {
+        set_error(P, kErrNoMem);
+        return -1;
+    }
+    return id;
+}
+
+DEV int64_t arena_alloc(const Params& P, int64_t count) {
+    uint64_t off = 0;
+    if (lane_id() == 0)
+        off = __hip_atomic_fetch_add(&P.ctl->arena_top, (uint64_t)count, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    off = __shfl(off, 0);
+    if (off + (uint64_t)count > P.arena_cap) {
+        set_error(P, kErrNoMem);
+        return -1;
+    }
+    return (int64_t)off;
+}
+
+DEV void stat_max(int64_t* p, int64_t v) {
+    if (lane_id() == 0) __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------ new RRRs
+
+struct FacOut {
+    int ok;
+    double growth;
+};
+
+// L+ D+ L+^T = L D L^T - tau I by the differential stationary qd transform
+// (Alg. 3.5), one shift per active lane, written to (Dp, Lp).  ok = the
+// factorisation exists (all pivots finite and nonzero); growth = ||D+||_max.
+DEV FacOut dstqds(Shared& S, const double* D, const double* L, int64_t n, double tau, bool act,
+                  double* Dp, double* Lp) {
+    double s = -tau, gmax = 0.0;
+    int ok = 1;
+    for (int64_t base = 0; base < n; base += kTile) {
+        load_rep_tile(S, D, L, base, n);
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        for (int t = 0; t < lim; ++t) {
+            const int64_t i = base + t;
+            const double dp = s + S.ta[t];
+            if (act) Dp[i] = dp;
+            ok &= (__builtin_isfinite(dp) && dp != 0.0) ? 1 : 0;
+            gmax = fmax(gmax, fabs(dp));
+            if (i < n - 1) {
+                const double lp = S.tb[t] / dp;
+                if (act) Lp[i] = lp;
+                ok &= __builtin_isfinite(lp) ? 1 : 0;
+                s = qd_q(s, dp) * S.tc[t] - tau;
+            }
+        }
+    }
+    FacOut o;
+    o.ok = ok;
+    o.growth = gmax;
+    return o;
+}
+
+// T - mu I = L D L^T by Gaussian elimination without pivoting; sgn > 0
+// requires every pivot positive, sgn < 0 every pivot negative (a definite
+// root, Sec. 3.1.2).
+DEV FacOut factor_T(Shared& S, const double* d, const double* e, int64_t n, double mu, int sgn,
+                    bool act, double* Dd, double* Ld) {
+    double dprev = 1.0, gmax = 0.0;
+    int ok = 1;
+    for (int64_t base = 0; base < n; base += kTile) {
+        load_T_tile(S, d, e, base, n);
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        for (int t = 0; t < lim; ++t) {
+            const int64_t i = base + t;
+            double dv;
+            if (i == 0) {
+                dv = S.ta[t] - mu;
+            } else {
+                const double lv = S.tc[t] / dprev;
+                if (act) Ld[i - 1] = lv;
+                dv = (S.ta[t] - mu) - lv * S.tc[t];
+            }
+            if (act) Dd[i] = dv;
+            ok &= (__builtin_isfinite(dv) && (sgn > 0 ? dv > 0.0 : dv < 0.0)) ? 1 : 0;
+            gmax = fmax(gmax, fabs(dv));
+            dprev = dv;
+        }
+    }
+    FacOut o;
+    o.ok = ok;
+    o.growth = gmax;
+    return o;
+}
+
+// ---------------------------------------------------------- classification
+
+DEV bool pair_split(double lo1, double hi1, double lo2, double hi2, double gaptol) {
+    // reldist(j, j+1) >= gaptol (Sec. 3.2.3); a zero scale means an infinite
+    // relative gap
+    const double den = fmax(fmax(fabs(lo1), fabs(hi1)), fmax(fabs(lo2), fabs(hi2)));
+    return (lo2 - hi1) >= gaptol * den;
+}
+
+// Partition a node's members into singletons and clusters (Alg. 4.2,
+// ClassifyEigenvalues) and enqueue the resulting S- and C-tasks.
+DEV void classify(Shared& S, const Params& P, int node_id) {
+    const int l = lane_id();
+    const Node nd = P.nodes[node_id];
+    const Block blk = P.blocks[nd.block];
+    const int64_t sb = blk.row0 - 1;
+    const int a = nd.a, b = nd.b;
+    const bool depth_cap = (nd.depth + 1 >= P.max_depth);
+    // pass 1: count singletons
+    int nsing = 0;
+    for (int base = a; base <= b; base += kWave) {
+        const int j = base + l;
+        bool single = false;
+        if (j <= b) {
+            const double lo = ld_rlx_d(P.lo + sb + j), hi = ld_rlx_d(P.hi + sb + j);
+            bool sbf = (j == a), saf = (j == b);
+            if (!sbf) sbf = pair_split(ld_rlx_d(P.lo + sb + j - 1), ld_rlx_d(P.hi + sb + j - 1), lo, hi, P.gaptol);
+            if (!saf) saf = pair_split(lo, hi, ld_rlx_d(P.lo + sb + j + 1), ld_rlx_d(P.hi + sb + j + 1), P.gaptol);
+            if (depth_cap) sbf = saf = true;
+            single = sbf && saf && j >= blk.w0 && j <= blk.w1;
+        }
+        nsing += __popcll(__ballot(single));
+    }
+    int64_t off = 0;
+    if (l == 0 && nsing > 0)
+        off = __hip_atomic_fetch_add(&P.ctl->slist_top, (int64_t)nsing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    off = __shfl(off, 0);
+    if (off + nsing > P.slist_cap) {
+        set_error(P, kErrNoMem);
+        return;
+    }
+    // pass 2: write the singleton list, gaps, and enqueue clusters
+    int pos = 0;
+    int open = -1;           // start of the cluster being scanned
+    int64_t largest = 0;
+    int ncl = 0, nunv = 0;
+    for (int base = a; base <= b; base += kWave) {
+        const int j = base + l;
+        bool sbf = false, saf = false;
+        double lo = 0.0, hi = 0.0, llo = 0.0, lhi = 0.0, rlo = 0.0, rhi = 0.0;
+        if (j <= b) {
+            lo = ld_rlx_d(P.lo + sb + j);
+            hi = ld_rlx_d(P.hi + sb + j);
+            sbf = (j == a);
+            saf = (j == b);
+            if (!sbf) {
+                llo = ld_rlx_d(P.lo + sb + j - 1);
+                lhi = ld_rlx_d(P.hi + sb + j - 1);
+                sbf = pair_split(llo, lhi, lo, hi, P.gaptol);
+            }
+            if (!saf) {
+                rlo = ld_rlx_d(P.lo + sb + j + 1);
+                rhi = ld_rlx_d(P.hi + sb + j + 1);
+                saf = pair_split(lo, hi, rlo, rhi, P.gaptol);
+            }
+            if (depth_cap && !(sbf && saf)) {
+                sbf = saf = true;
+                nunv += 1;
+            }
+        }
+        const bool in = (j <= b);
+        const bool single = in && sbf && saf && j >= blk.w0 && j <= blk.w1;
+        const uint64_t sm = __ballot(single);
+        if (single) {
+            const int k = pos + __popcll(sm & ((1ull << l) - 1ull));
+            P.slist[off + k] = (int32_t)(sb + j);
+            const double lg = (j == a) ? nd.lgap : (lo - lhi);
+            const double rg = (j == b) ? nd.rgap : (rlo - hi);
+            P.gap[sb + j] = fmin(lg, rg);
+        }
+        pos += __popcll(sm);
+        // cluster boundaries, in order
+        const uint64_t starts = __ballot(in && sbf && !saf);
+        const uint64_t ends = __ballot(in && !sbf && saf);
+        uint64_t ev = starts | ends;
+        while (ev) {
+            const int t = __ffsll((unsigned long long)ev) - 1;
+            ev &= ev - 1ull;
+            const int jj = base + t;
+            if ((starts >> t) & 1ull) {
+                open = jj;
+            } else if (open >= 0) {
+                const int p = open, q = jj;
+                open = -1;
+                if ((int64_t)(q - p + 1) > largest) largest = q - p + 1;
+                if (q >= blk.w0 && p <= blk.w1) {
+                    ++ncl;
+                    Task tk;
+                    tk.type = kTaskCluster;
+                    tk.node = node_id;
+                    tk.a = p;
+                    tk.b = q;
+                    push_one(P, kQCluster, tk);
+                }
+            }
+        }
+    }
+    // singleton bundles of up to 64
+    const int nb = (nsing + kWave - 1) / kWave;
+    push_batch(P, kQSingle, nb, [&](int k) {
+        Task t;
+        t.type = kTaskSingle;
+        t.node = node_id;
+        t.a = (int)(off + (int64_t)k * kWave);
+        const int rem = nsing - k * kWave;
+        t.b = rem < kWave ? rem : kWave;
+        return t;
+    });
+    stat_max(&P.ctl->largest_cluster, largest);
+    add_stat(&P.ctl->n_unverified, nunv > 0 ? 1 : 0);
+    (void)ncl;
+}
+
+// ---------------------------------------------------------------- tasks
+
+DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
+    const int l = lane_id();
+    const Block blk = P.blocks[bid];
+    const int64_t n = blk.n;
+    const double* d = P.d + blk.row0;
+    const double* e = P.e + blk.row0;
+    // Gershgorin interval of the block (App. B, Alg. B.3)
+    double gl = __builtin_inf(), gu = -__builtin_inf();
+    for (int64_t i = l; i < n; i += kWave) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+        gl = fmin(gl, d[i] - r);
+        gu = fmax(gu, d[i] + r);
+    }
+    gl = wave_min(gl);
+    gu = wave_max(gu);
+    const double bnorm = fmax(fabs(gl), fabs(gu));
+    const double slack = (2.0 * (double)n + 10.0) * bnorm * kEps;
+    gl -= slack;
+    gu += slack;
+    const double spdiam = gu - gl;
+    // extremal eigenvalues by multisection on NegCount(T): lanes 0-31 lambda_1,
+    // lanes 32-63 lambda_n, until the brackets are 4 n eps bnorm wide
+    double delta = 4.0 * (double)n * kEps * fmax(bnorm, kSafmin);
+    double lo1 = gl, hi1 = gu, lon = gl, hin = gu;
+    const int half = l >> 5, t = l & 31;
+    for (int pass = 0; pass < 200; ++pass) {
+        if (hi1 - lo1 <= delta && hin - lon <= delta) break;
+        const double lo = half ? lon : lo1, hi = half ? hin : hi1;
+        const double sig = lo + (hi - lo) * (double)(t + 1) / 33.0;
+        const int c = negcount_T(S, d, e, n, sig);
+        steps += n * kWave;
+        const uint64_t ge = __ballot(c >= (half ? (int)n : 1));
+        const uint64_t g0 = ge & 0xffffffffull, g1 = ge >> 32;
+        const int t0 = g0 ? __ffsll((unsigned long long)g0) - 1 : 32;
+        const int t1 = g1 ? __ffsll((unsigned long long)g1) - 1 : 32;
+        const double h0 = __shfl(sig, t0 < 32 ? t0 : 31), l0 = __shfl(sig, t0 > 0 ? t0 - 1 : 0);
+        const double h1 = __shfl(sig, 32 + (t1 < 32 ? t1 : 31)), l1 = __shfl(sig, 32 + (t1 > 0 ? t1 - 1 : 0));
+        if (t0 < 32) hi1 = h0;
+        if (t0 > 0) lo1 = l0;
+        if (t1 < 32) hin = h1;
+        if (t1 > 0) lon = l1;
+    }
+    // root shift mu: just outside either end, so that T - mu I is definite
+    const int64_t off = arena_alloc(P, 4 * n);
+    if (off < 0) return;
+    double* C0 = P.arena + off;
+    double* C1 = P.arena + off + 2 * n;
+    double mul = lo1 - delta, mur = hin + delta;
+    int side = -1;
+    for (int tr = 0; tr < 16 && side < 0; ++tr) {
+        const double mu = (l == 0) ? mul : mur;
+        const FacOut f = factor_T(S, d, e, n, mu, (l == 0) ? 1 : -1, l < 2,
+                                  (l == 0) ? C0 : C1, ((l == 0) ? C0 : C1) + n);
+        steps += 2 * n;
+        const int ok0 = __shfl(f.ok, 0), ok1 = __shfl(f.ok, 1);
+        const double g0 = __shfl(f.growth, 0), g1 = __shfl(f.growth, 1);
+        if (ok0 && ok1) side = (g1 < g0) ? 1 : 0;
+        else if (ok0) side = 0;
+        else if (ok1) side = 1;
+        else {
+            delta *= 2.0;
+            mul = lo1 - delta;
+            mur = hin + delta;
+        }
+    }
+    if (side < 0) {
+        set_error(P, kErrInternal);
+        return;
+    }
+    const double mu = side ? mur : mul;
+    double* Dr = side ? C1 : C0;
+    double* Lr = Dr + n;
+    // "random" relative perturbation of every datum by at most xi*eps
+    // (Alg. 3.2, line 2)
+    const double amp = P.xi * kEps;
+    for (int64_t i = l; i < n; i += kWave) {
+        const uint64_t g = (uint64_t)(blk.row0 + i);
+        Dr[i] = Dr[i] * (1.0 + amp * unit_pm1(P.seed, 2 * g));
+        if (i < n - 1) Lr[i] = Lr[i] * (1.0 + amp * unit_pm1(P.seed, 2 * g + 1));
+    }
+    __threadfence();
+    __syncthreads();
+    // root brackets: the definite root's spectrum lies between 0 and the
+    // shifted Gershgorin end; confirm both ends by counts, widen if needed
+    double rlo, rhi;
+    double pad = 16.0 * (double)n * (P.xi + 1.0) * kEps;
+    for (int tr = 0; tr < 12; ++tr) {
+        if (side == 0) { rlo = 0.0; rhi = (gu - mu) * (1.0 + pad) + kSafmin; }
+        else { rhi = 0.0; rlo = (gl - mu) * (1.0 + pad) - kSafmin; }
+        const double sig = (l == 0) ? rlo : rhi;
+        const int c = negcount_rep(S, Dr, Lr, n, sig);
+        steps += 2 * n;
+        const int c0 = __shfl(c, 0), c1 = __shfl(c, 1);
+        if (c0 == 0 && c1 == (int)n) break;
+        pad *= 16.0;
+    }
+    const int id = new_node(P);
+    if (id < 0) return;
+    if (l == 0) {
+        Node nd;
+        nd.data = side ? off + 2 * n : off;
+        nd.block = bid;
+        nd.depth = 0;
+        nd.a = (int32_t)blk.k0;
+        nd.b = (int32_t)blk.k1;
+        nd.parent = -1;
+        nd.pending = 0;
+        nd.sigma = mu;
+        nd.lgap = __builtin_inf();
+        nd.rgap = __builtin_inf();
+        nd.spdiam = spdiam;
+        nd.pad = 0.0;
+        P.nodes[id] = nd;
+        P.blocks[bid].root = id;
+    }
+    const int64_t sb = blk.row0 - 1;
+    for (int64_t j = blk.k0 + l; j <= blk.k1; j += kWave) {
+        P.lo[sb + j] = rlo;
+        P.hi[sb + j] = rhi;
+        P.vflag[sb + j] = 3;
+    }
+    add_stat(&P.ctl->n_nodes, 1);
+    push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull);
+}
+
+DEV void load_members(Shared& S, const Params& P, int64_t sb, int a, int M) {
+    const int l = lane_id();
+    if (l < M) {
+        const int j = a + l;
+        const int64_t slot = sb + j;
+        S.m_j[l] = j;
+        S.m_slot[l] = slot;
+        S.m_lo[l] = ld_rlx_d(P.lo + slot);
+        S.m_hi[l] = ld_rlx_d(P.hi + slot);
+        S.m_flag[l] = P.vflag[slot];
+    }
+    __syncthreads();
+}
+
+DEV void task_refine(Shared& S, const Params& P, int node_id, int a, int braw, int64_t& steps) {
+    const int l = lane_id();
+    const int mode = (braw >> 30) & 1;
+    const int b = braw & 0x3fffffff;
+    const Node nd = P.nodes[node_id];
+    const Block blk = P.blocks[nd.block];
+    const int64_t n = blk.n;
+    const double* D = P.arena + nd.data;
+    const double* L = D + n;
+    const int M = b - a + 1;
+    const int64_t sb = blk.row0 - 1;
+    load_members(S, P, sb, a, M);
+    MemberCtx C;
+    C.mode = mode;
+    C.na = nd.a;
+    C.nb = nd.b;
+    C.slot_base = sb;
+    C.publish = true;
+    refine_members(S, P, D, L, n, M, C, steps);
+    if (l < M) P.vflag[S.m_slot[l]] = (uint8_t)S.m_flag[l];
+    if (mode == kModeFull && !P.jobz && l < M) {
+        // eigenvalues only: the root's bisection result is final
+        const int j = S.m_j[l];
+        if (j >= blk.w0 && j <= blk.w1) {
+            const Problem& pr = P.probs[blk.prob];
+            const int64_t col = blk.col0 + (j - blk.w0);
+            P.w[pr.woff + col] = nd.sigma + (S.m_lo[l] + 0.5 * (S.m_hi[l] - S.m_lo[l]));
+        }
+    }
+    __threadfence();
+    int last = 0;
+    if (l == 0)
+        last = (__hip_atomic_fetch_add(&P.nodes[node_id].pending, -1, __ATOMIC_ACQ_REL,
+                                       __HIP_MEMORY_SCOPE_AGENT) == 1) ? 1 : 0;
+    last = __shfl(last, 0);
+    if (last && mode == kModeClass) {
+        __threadfence();
+        classify(S, P, node_id);
+    }
+}
+
+DEV double grow_lo(double x, double nu) { return x - nu * fabs(x); }
+DEV double grow_hi(double x, double nu) { return x + nu * fabs(x); }
+
+DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t& steps) {
+    const int l = lane_id();
+    const Node par = P.nodes[pid];
+    const Block blk = P.blocks[par.block];
+    const int64_t n = blk.n;
+    const double* D = P.arena + par.data;
+    const double* L = D + n;
+    const int64_t sb = blk.row0 - 1;
+    // 1. the cluster's end eigenvalues to full accuracy (Alg. 3.8, line 1)
+    if (l < 2) {
+        const int j = (l == 0) ? p : q;
+        const int64_t slot = sb + j;
+        S.m_j[l] = j;
+        S.m_slot[l] = slot;
+        S.m_lo[l] = ld_rlx_d(P.lo + slot);
+        S.m_hi[l] = ld_rlx_d(P.hi + slot);
+        S.m_flag[l] = P.vflag[slot];
+    }
+    __syncthreads();
+    MemberCtx C;
+    C.mode = kModeFull;
+    C.na = -1;
+    C.nb = -1;
+    C.slot_base = sb;
+    C.publish = true;
+    refine_members(S, P, D, L, n, 2, C, steps);
+    const double lo_p = S.m_lo[0], hi_p = S.m_hi[0];
+    const double lo_q = S.m_lo[1], hi_q = S.m_hi[1];
+    // gaps to the neighbours outside the cluster (shift invariant)
+    const double lgap = (p > par.a) ? lo_p - ld_rlx_d(P.hi + sb + p - 1) : par.lgap;
+    const double rgap = (q < par.b) ? ld_rlx_d(P.lo + sb + q + 1) - hi_q : par.rgap;
+    // 2. shifts just outside both ends; keep the candidate with the smaller
+    //    element growth; back off while the growth is too large (Alg. 3.8)
+    const int64_t off = arena_alloc(P, 4 * n);
+    if (off < 0) return;
+    double* C0 = P.arena + off;
+    double* C1 = P.arena + off + 2 * n;
+    double taul = lo_p - 100.0 * kEps * fabs(lo_p);
+    double taur = hi_q + 100.0 * kEps * fabs(hi_q);
+    const double spd = par.spdiam;
+    const double thresh = 8.0 * spd;
+    double best = __builtin_inf(), best_tau = 0.0;
+    int chosen = -1;
+    double tau = 0.0;
+    for (int tr = 0; tr < P.max_tries; ++tr) {
+        const double tl = (l == 0) ? taul : taur;
+        const FacOut f = dstqds(S, D, L, n, tl, l < 2, (l == 0) ? C0 : C1, ((l == 0) ? C0 : C1) + n);
+        steps += 2 * n;
+        const int ok0 = __shfl(f.ok, 0), ok1 = __shfl(f.ok, 1);
+        const double g0 = __shfl(f.growth, 0), g1 = __shfl(f.growth, 1);
+        int pick = -1;
+        if (ok0 && ok1) pick = (g1 < g0) ? 1 : 0;
+        else if (ok0) pick = 0;
+        else if (ok1) pick = 1;
+        if (pick >= 0) {
+            const double g = pick ? g1 : g0;
+            const double tp = pick ? taur : taul;
+            if (g < best) { best = g; best_tau = tp; }
+            if (g <= thresh) { chosen = pick; tau = tp; break; }
+        }
+        const double dl = ldexp(100.0 * kEps * fabs(lo_p) + kEps * spd, tr);
+        const double dr = ldexp(100.0 * kEps * fabs(hi_q) + kEps * spd, tr);
+        taul -= dl;
+        taur += dr;
+    }
+    int unverified = 0;
+    if (chosen < 0) {
+        if (!(best < __builtin_inf())) {
+            set_error(P, kErrNoConv);
+            return;
+        }
+        // no candidate passed: the least element growth (Alg. 3.8, last line)
+        dstqds(S, D, L, n, best_tau, l == 0, C0, C0 + n);
+        steps += n;
+        chosen = 0;
+        tau = best_tau;
+        unverified = 1;
+    }
+    const int id = new_node(P);
+    if (id < 0) return;
+    if (l == 0) {
+        Node nd;
+        nd.data = off + (chosen ? 2 * n : 0);
+        nd.block = par.block;
+        nd.depth = par.depth + 1;
+        nd.a = p;
+        nd.b = q;
+        nd.parent = pid;
+        nd.pending = 0;
+        nd.sigma = par.sigma + tau;
+        nd.lgap = lgap;
+        nd.rgap = rgap;
+        nd.spdiam = spd;
+        nd.pad = 0.0;
+        P.nodes[id] = nd;
+    }
+    // 3. child brackets: (lambda(1 -+ nu) - tau)(1 -+ nu), nu = 10 k_rr n eps
+    //    with k_rr = 10, widened outward (Sec. 3.2.3)
+    const double nu = 100.0 * (double)n * kEps;
+    for (int j = p + l; j <= q; j += kWave) {
+        const int64_t slot = sb + j;
+        double lo = ld_rlx_d(P.lo + slot), hi = ld_rlx_d(P.hi + slot);
+        if (j == p) { lo = lo_p; hi = hi_p; }
+        if (j == q) { lo = lo_q; hi = hi_q; }
+        st_rlx_d(P.lo + slot, grow_lo(grow_lo(lo, nu) - tau, nu));
+        st_rlx_d(P.hi + slot, grow_hi(grow_hi(hi, nu) - tau, nu));
+        P.vflag[slot] = 0;
+    }
+    add_stat(&P.ctl->n_nodes, 1);
+    add_stat(&P.ctl->n_unverified, unverified);
+    if (l == 0) {
+        __hip_atomic_fetch_max(&P.ctl->dmax, par.depth + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    push_slices(P, id, p, q, kModeClass);
+}
+
+// A bundle of singletons of one node, one per lane (Alg. 4.3): Rayleigh
+// quotient iteration on twisted factorisations with the inertia of Delta_r
+// guarding the direction; bisection to full accuracy plus one more Getvec as
+// the fallback; then the eigenvector (Alg. 3.7) straight into Z.
+DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, int64_t& steps) {
+    const int l = lane_id();
+    const Node nd = P.nodes[node_id];
+    const Block blk = P.blocks[nd.block];
+    const Problem pr = P.probs[blk.prob];
+    const int64_t n = blk.n;
+    const double* D = P.arena + nd.data;
+    const double* L = D + n;
+    const int64_t sb = blk.row0 - 1;
+    const bool act = l < cnt;
+    const int64_t slot = P.slist[off + (act ? l : 0)];
+    const int j = (int)(slot - sb);
+    double lo = ld_rlx_d(P.lo + slot), hi = ld_rlx_d(P.hi + slot);
+    const double gap = P.gap[slot];
+    int vf = P.vflag[slot];
+    double lam = lo + 0.5 * (hi - lo);
+    CkPtr ck;
+    ck.base = P.ck + pr.ck_base + (slot - pr.ck_slot0);
+    ck.stride = pr.ck_stride;
+    const double tol1 = (double)n * kEps, tol2 = 2.0 * kEps;
+    bool done = !act, force = false;
+    int r = 0;
+    double nrm2 = 1.0;
+    int64_t nrqi = 0, nfb = 0;
+    for (int it = 0; it < P.max_rqi + 4; ++it) {
+        if (__ballot(!done) == 0ull) break;
+        const bool live = !done;
+        const TwistOut tw = twisted(S, D, L, n, lam, live, ck, steps);
+        nrqi += __popcll(__ballot(live));
+        bool fb = false;
+        if (live) {
+            const bool below = tw.neg >= j;       // lambda_j < lam
+            if (below) { hi = fmin(hi, lam); vf |= 2; }
+            else { lo = fmax(lo, lam); vf |= 1; }
+            const bool fin = __builtin_isfinite(tw.nrm2) && tw.nrm2 > 0.0;
+            const double resid = fin ? fabs(tw.gam) / sqrt(tw.nrm2) : __builtin_inf();
+            const double rqc = fin ? tw.gam / tw.nrm2 : 0.0;
+            if (force || (fin && (resid <= tol1 * gap || fabs(rqc) <= tol2 * fabs(lam)))) {
+                done = true;
+                r = tw.r;
+                nrm2 = tw.nrm2;
+            } else {
+                const bool sign_ok = below ? (rqc <= 0.0) : (rqc >= 0.0);
+                const double cand = lam + rqc;
+                if (fin && sign_ok && cand >= lo && cand <= hi && it < P.max_rqi) lam = cand;
+                else fb = true;
+            }
+        }
+        // bisection fallback to full accuracy for the lanes that need it
+        const uint64_t fm = __ballot(fb);
+        if (fm) {
+            const int k = __popcll(fm & ((1ull << l) - 1ull));
+            if (fb) {
+                S.m_j[k] = j;
+                S.m_slot[k] = slot;
+                S.m_lo[k] = lo;
+                S.m_hi[k] = hi;
+                S.m_flag[k] = vf;
+            }
+            __syncthreads();
+            MemberCtx C;
+            C.mode = kModeFull;
+            C.na = -1;
+            C.nb = -1;
+            C.slot_base = sb;
+            C.publish = false;
+            refine_members(S, P, D, L, n, __popcll(fm), C, steps);
+            if (fb) {
+                lo = S.m_lo[k];
+                hi = S.m_hi[k];
+                vf = S.m_flag[k];
+                lam = lo + 0.5 * (hi - lo);
+                force = true;
+            }
+            nfb += __popcll(fm);
+            __syncthreads();
+        }
+    }
+    if (__ballot(act && !done) != 0ull) {
+        set_error(P, kErrNoConv);
+        return;
+    }
+    const int64_t col = blk.col0 + (j - blk.w0);
+    if (P.jobz) {
+        double* zcol = P.Z + pr.zoff + (act ? col : 0) * pr.ldz + (blk.row0 - pr.row0);
+        const bool fin = __builtin_isfinite(nrm2) && nrm2 > 0.0;
+        if (__ballot(act && !fin) != 0ull) {
+            // a zero pivot spoiled the nested norm: sum the squares directly
+            const double ss = solve_vector(S, D, L, n, lam, act, r, 1.0, ck, zcol, false, steps);
+            if (!fin) nrm2 = ss;
+        }
+        const double scale = 1.0 / sqrt(nrm2);
+        solve_vector(S, D, L, n, lam, act, r, scale, ck, zcol, true, steps);
+        if (act && (pr.flags & 1)) {
+            // several blocks: the rest of the column is zero
+            double* zc = P.Z + pr.zoff + col * pr.ldz;
+            const int64_t r0 = blk.row0 - pr.row0;
+            for (int64_t i = 0; i < r0; ++i) zc[i] = 0.0;
+            for (int64_t i = r0 + n; i < pr.n; ++i) zc[i] = 0.0;
+        }
+    }
+    if (act) P.w[pr.woff + col] = nd.sigma + lam;
+    add_stat(&P.ctl->n_rqi, nrqi);
+    add_stat(&P.ctl->n_fallback, nfb);
+}
+
+}  // namespace mrrr
+
+// ---------------------------------------------------------------- kernels
+
+using namespace mrrr;
+
+// The persistent worker: one wavefront per workgroup, looping over the task
+// queues until no task is pending (or an error / the watchdog stops it).
+extern "C" __global__ __launch_bounds__(64) void mrrr_tree_kernel(Params P) {
+    __shared__ Shared S;
+    const int l = lane_id();
+    const uint64_t t0 = wall_clock64();
+    int64_t steps = 0, ntask = 0, nsingle = 0;
+    for (;;) {
+        if (l == 0) {
+            int status = 0;
+            for (;;) {
+                if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { status = 2; break; }
+                bool got = false;
+                for (int qq = 0; qq < kNumQ && !got; ++qq) got = try_pop(P, qq, &S.task);
+                if (got) { status = 1; break; }
+                if (__hip_atomic_load(&P.ctl->pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) { status = 2; break; }
+                if (wall_clock64() - t0 > P.timeout_ticks) {
+                    int32_t expect = 0;
+                    __hip_atomic_compare_exchange_strong(&P.ctl->error, &expect, (int32_t)kErrTimeout,
+                                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    status = 2;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            S.ibc[0] = status;
+        }
+        __syncthreads();
+        const int status = S.ibc[0];
+        const Task tk = S.task;
+        __syncthreads();
+        if (status != 1) break;
+        __threadfence();
+        switch (tk.type) {
+            case kTaskRoot: task_root(S, P, tk.node, steps); break;
+            case kTaskRefine: task_refine(S, P, tk.node, tk.a, tk.b, steps); break;
+            case kTaskCluster: task_cluster(S, P, tk.node, tk.a, tk.b, steps); break;
+            case kTaskSingle: task_single(S, P, tk.node, tk.a, tk.b, steps); ++nsingle; break;
+            default: set_error(P, kErrInternal); break;
+        }
+        __threadfence();
+        __syncthreads();
+        if (l == 0) __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)-1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        ++ntask;
+    }
+    add_stat(&P.ctl->qd_steps, steps);
+    add_stat(&P.ctl->n_tasks, ntask);
+    add_stat(&P.ctl->n_single, nsingle);
+}
+
+// Resets the control block and the queue cells (no memset nodes, so that the
+// sequence can be captured in a graph).
+extern "C" __global__ void mrrr_init_kernel(Params P) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    if (tid == 0) {
+        Ctl c;
+        uint64_t* raw = (uint64_t*)&c;
+        for (size_t k = 0; k < sizeof(Ctl) / 8; ++k) raw[k] = 0;
+        *P.ctl = c;
+    }
+    for (int qq = 0; qq < kNumQ; ++qq)
+        for (int64_t i = tid; i < (int64_t)P.qcap[qq]; i += nth) P.seq[qq][i] = (uint64_t)i;
+}
+
+// Per problem: splitting into irreducible blocks (Sec. 3.2.1), index ranges
+// per block, trivial 1x1 blocks, and one root task per remaining block.
+extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
+    __shared__ Shared S;
+    const int l = lane_id();
+    const int p = blockIdx.x;
+    Problem* pr = P.probs + p;
+    const int64_t n = pr->n;
+    if (n <= 0) {
+        if (l == 0) { pr->m = 0; pr->nblocks = 0; }
+        return;
+    }
+    const double* d = P.d + pr->row0;
+    const double* e = P.e + pr->row0;
+    double gl = __builtin_inf(), gu = -__builtin_inf();
+    for (int64_t i = l; i < n; i += kWave) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+        gl = fmin(gl, d[i] - r);
+        gu = fmax(gu, d[i] + r);
+    }
+    gl = wave_min(gl);
+    gu = wave_max(gu);
+    int bad_d = 0, bad_e = 0;
+    for (int64_t i = l; i < n; i += kWave) {
+        bad_d |= __builtin_isfinite(d[i]) ? 0 : 1;
+        if (i < n - 1) bad_e |= __builtin_isfinite(e[i]) ? 0 : 1;
+    }
+    if (wave_or(bad_d) || wave_or(bad_e)) {
+        if (l == 0) { pr->m = 0; pr->nblocks = 0; }
+        set_error(P, wave_or(bad_d) ? kErrBadD : kErrBadE);
+        return;
+    }
+    const double bnorm = fmax(fabs(gl), fabs(gu));
+    const double tol = kEps * sqrt((double)n) * bnorm;
+    Block* B = P.blocks + pr->row0;
+    int nb = 0;
+    int64_t start = 0;
+    for (int64_t base = 0; base < n - 1; base += kWave) {
+        const int64_t i = base + l;
+        const bool sp = (i < n - 1) && fabs(e[i]) <= tol;
+        uint64_t mk = __ballot(sp);
+        while (mk) {
+            const int t = __ffsll((unsigned long long)mk) - 1;
+            mk &= mk - 1ull;
+            const int64_t is = base + t;
+            if (l == 0) {
+                B[nb].prob = p;
+                B[nb].root = -1;
+                B[nb].row0 = pr->row0 + start;
+                B[nb].n = is - start + 1;
+            }
+            ++nb;
+            start = is + 1;
+        }
+    }
+    if (l == 0) {
+        B[nb].prob = p;
+        B[nb].root = -1;
+        B[nb].row0 = pr->row0 + start;
+        B[nb].n = n - start;
+    }
+    ++nb;
+    __threadfence_block();
+    __syncthreads();
+    // index ranges per block
+    int64_t m = 0;
+    int err = 0;
+    if (pr->range == 2 && nb > 1) err = kErrNotImpl;
+    for (int b = 0; b < nb && !err; ++b) {
+        const int64_t nbk = B[b].n;
+        int64_t w0, w1;
+        if (pr->range == 0) {
+            w0 = 1;
+            w1 = nbk;
+        } else if (pr->range == 1) {
+            const double sig = (l == 0) ? pr->vl : pr->vu;
+            const int c = negcount_T(S, P.d + B[b].row0, P.e + B[b].row0, nbk, sig);
+            w0 = (int64_t)__shfl(c, 0) + 1;
+            w1 = (int64_t)__shfl(c, 1);
+        } else {
+            w0 = pr->il;
+            w1 = pr->iu;
+        }
+        if (l == 0) {
+            B[b].w0 = w0;
+            B[b].w1 = w1;
+            B[b].k0 = w0 > 1 ? w0 - 1 : 1;
+            B[b].k1 = w1 < nbk ? w1 + 1 : nbk;
+            B[b].col0 = (pr->range == 0) ? (B[b].row0 - pr->row0) : m;
+        }
+        if (w1 >= w0) m += w1 - w0 + 1;
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (l == 0) {
+        pr->m = err ? 0 : m;
+        pr->nblocks = nb;
+        pr->bnorm = bnorm;
+        pr->flags = (nb > 1) ? 1 : 0;
+        __hip_atomic_fetch_add(&P.ctl->n_blocks, (int64_t)nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (err) {
+        set_error(P, err);
+        return;
+    }
+    for (int b = 0; b < nb; ++b) {
+        const Block bk = B[b];
+        if (bk.w1 < bk.w0) continue;
+        if (bk.n == 1) {
+            // a 1x1 block: its eigenpair is (d_i, e_i)
+            if (l == 0) P.w[pr->woff + bk.col0] = P.d[bk.row0];
+            if (P.jobz) {
+                double* zc = P.Z + pr->zoff + bk.col0 * pr->ldz;
+                for (int64_t i = l; i < n; i += kWave) zc[i] = (i == bk.row0 - pr->row0) ? 1.0 : 0.0;
+            }
+            continue;
+        }
+        Task t;
+        t.type = kTaskRoot;
+        t.node = (int)(pr->row0 + b);
+        t.a = 0;
+        t.b = 0;
+        push_one(P, kQCluster, t);
+    }
+}
+
+// After the tree: eigenvalues of several blocks (or a rare out-of-order pair)
+// are put in ascending order, Z's columns permuted along (in place, one
+// column buffer per problem).
+extern "C" __global__ __launch_bounds__(64) void mrrr_finalize_kernel(Params P) {
+    const int l = lane_id();
+    const Problem pr = P.probs[blockIdx.x];
+    const int64_t m = pr.m;
+    if (m < 2) return;
+    double* w = P.w + pr.woff;
+    int unsorted = 0;
+    for (int64_t i = l; i + 1 < m; i += kWave) unsorted |= (w[i] > w[i + 1]) ? 1 : 0;
+    if (!wave_or(unsorted)) return;
+    int32_t* rank = P.perm + pr.row0;
+    int32_t* src = P.perm + P.total_rows + pr.row0;
+    for (int64_t i = l; i < m; i += kWave) {
+        const double wi = w[i];
+        int64_t rk = 0;
+        for (int64_t k = 0; k < m; ++k) rk += (w[k] < wi || (w[k] == wi && k < i)) ? 1 : 0;
+        rank[i] = (int32_t)rk;
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int64_t i = l; i < m; i += kWave) src[rank[i]] = (int32_t)i;
+    __threadfence_block();
+    __syncthreads();
+    double* buf = P.colbuf + pr.row0;
+    for (int64_t i = l; i < m; i += kWave) buf[i] = w[src[i]];
+    __threadfence_block();
+    __syncthreads();
+    for (int64_t i = l; i < m; i += kWave) w[i] = buf[i];
+    __threadfence_block();
+    __syncthreads();
+    if (!P.jobz) return;
+    const int64_t n = pr.n, ldz = pr.ldz;
+    double* Z = P.Z + pr.zoff;
+    for (int64_t p0 = 0; p0 < m; ++p0) {
+        int32_t s0 = src[p0];
+        if (s0 < 0 || s0 == p0) continue;
+        for (int64_t i = l; i < n; i += kWave) buf[i] = Z[p0 * ldz + i];
+        int64_t pp = p0;
+        for (int64_t guard = 0; guard <= m; ++guard) {
+            const int32_t s = src[pp];
+            __syncthreads();
+            if (l == 0) src[pp] = -1;
+            __threadfence_block();
+            __syncthreads();
+            if (s == p0) {
+                for (int64_t i = l; i < n; i += kWave) Z[pp * ldz + i] = buf[i];
+                break;
+            }
+            for (int64_t i = l; i < n; i += kWave) Z[pp * ldz + i] = Z[(int64_t)s * ldz + i];
+            pp = s;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+// Sign convention: the entry of largest magnitude of each column positive
+// (ties to the lowest row).  One wavefront per column.
+extern "C" __global__ __launch_bounds__(64) void mrrr_sign_kernel(Params P, int64_t ncols_total) {
+    const int l = lane_id();
+    for (int64_t g = blockIdx.x; g < ncols_total; g += gridDim.x) {
+        // column g is slot-ordered: find its problem
+        int a = 0, b = P.nprob - 1;
+        while (a < b) {
+            const int mid = (a + b + 1) >> 1;
+            if (P.probs[mid].row0 <= g) a = mid; else b = mid - 1;
+        }
+        const Problem& pr = P.probs[a];
+        const int64_t col = g - pr.row0;
+        if (col >= pr.m) continue;
+        double* z = P.Z + pr.zoff + col * pr.ldz;
+        double best = -1.0;
+        int64_t bi = 0;
+        for (int64_t i = l; i < pr.n; i += kWave) {
+            const double v = fabs(z[i]);
+            if (v > best) { best = v; bi = i; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o);
+            const int64_t oi = __shfl_xor(bi, o);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        const bool neg = z[bi] < 0.0;
+        if (neg)
+            for (int64_t i = l; i < pr.n; i += kWave) z[i] = -z[i];
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+namespace mrrr {
+
+hipError_t launch_init(const Params& P, hipStream_t s) {
+    uint64_t mx = 1;
+    for (int q = 0; q < kNumQ; ++q) mx = P.qcap[q] > mx ? P.qcap[q] : mx;
+    int grid = (int)((mx + 255) / 256);
+    if (grid > 4096) grid = 4096;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(mrrr_init_kernel, dim3(grid), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const Params& P, hipStream_t s) {
+    hipLaunchKernelGGL(mrrr_setup_kernel, dim3(P.nprob), dim3(kWave), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree(const Params& P, hipStream_t s) {
+    hipLaunchKernelGGL(mrrr_tree_kernel, dim3(P.nworkers), dim3(kWave), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Params& P, hipStream_t s) {
+    hipLaunchKernelGGL(mrrr_finalize_kernel, dim3(P.nprob), dim3(kWave), 0, s, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_sign(const Params& P, int64_t ncols_total, hipStream_t s) {
+    int64_t g = ncols_total < 65536 ? ncols_total : 65536;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(mrrr_sign_kernel, dim3((unsigned)g), dim3(kWave), 0, s, P, ncols_total);
+    return hipGetLastError();
+}
+
+hipError_t tree_occupancy(int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, mrrr_tree_kernel, kWave, 0);
+}
+
+}  // namespace mrrr
