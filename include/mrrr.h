@@ -68,14 +68,33 @@ typedef struct {
     double perturb_xi;       /* root perturbation bound in units of eps, 8 (Alg. 3.2) */
     uint64_t seed;           /* seed of the root perturbation */
     int32_t max_rqi;         /* Rayleigh-quotient steps before bisection, 10 */
-    int32_t max_shift_tries; /* shift candidates for a new RRR, 8 (Alg. 3.8) */
+    int32_t max_shift_tries; /* back-off levels per side for a new RRR, 16 (Alg. 3.8) */
     int32_t max_depth;       /* deepest representation tree allowed, 64 */
     int32_t workers;         /* persistent-kernel wavefronts; 0 = fill the GPU */
     int32_t slice_min;       /* smallest refinement slice (eigenvalues), 2 */
     int32_t slice_max;       /* largest refinement slice (eigenvalues), 64 */
     double timeout_s;        /* device watchdog for one solve, seconds (30) */
     double arena_scale;      /* node-pool size factor (1.0); grows on ENOMEM */
+    void *trace;             /* device, optional: trace_cap mrrr_trace_t records */
+    int64_t trace_cap;       /* 0 = no trace */
 } mrrr_options_t;
+
+/* One record per executed device task (the per-task timeline of the
+ * thesis' execution traces, Sec. 4.1.4).  Written in completion order;
+ * stats->n_tasks tells how many tasks ran (records beyond trace_cap are
+ * dropped). */
+typedef struct {
+    int32_t type;    /* 1 root, 2 refinement slice, 3 cluster, 4 singleton bundle */
+    int32_t worker;  /* workgroup (wavefront) index */
+    int32_t node;    /* representation the task worked on (root: block) */
+    int32_t depth;   /* its depth in the representation tree */
+    int32_t a, b;    /* member range (inclusive) or bundle offset and size */
+    int64_t t0, t1;  /* device wall-clock ticks (hipDeviceAttributeWallClockRate) */
+    double x0, x1;   /* cluster: chosen shift tau and element growth max|D+|;
+                        root: shift mu and spectral diameter */
+    int32_t flags;   /* cluster: 1 = accepted without passing the growth test */
+    int32_t child;   /* cluster: id of the new representation */
+} mrrr_trace_t;
 
 /* Per-call statistics (host struct, filled after the work completes). */
 typedef struct {

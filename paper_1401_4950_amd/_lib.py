@@ -31,7 +31,15 @@ class Options(ctypes.Structure):
         ("max_depth", ctypes.c_int32), ("workers", ctypes.c_int32),
         ("slice_min", ctypes.c_int32), ("slice_max", ctypes.c_int32),
         ("timeout_s", ctypes.c_double), ("arena_scale", ctypes.c_double),
+        ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int64),
     ]
+
+
+#: numpy dtype of one mrrr_trace_t record
+TRACE_FIELDS = [("type", "<i4"), ("worker", "<i4"), ("node", "<i4"), ("depth", "<i4"),
+                ("a", "<i4"), ("b", "<i4"), ("t0", "<i8"), ("t1", "<i8"),
+                ("x0", "<f8"), ("x1", "<f8"), ("flags", "<i4"), ("child", "<i4")]
+TRACE_BYTES = 64
 
 
 class Stats(ctypes.Structure):

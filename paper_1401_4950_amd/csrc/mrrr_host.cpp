@@ -12,6 +12,8 @@
 #include "../../include/mrrr.h"
 #include "mrrr_internal.h"
 
+static_assert(sizeof(mrrr::TraceRec) == sizeof(mrrr_trace_t), "trace record layout");
+
 namespace mrrr {
 hipError_t launch_init(const Params& P, hipStream_t s);
 hipError_t launch_setup(const Params& P, hipStream_t s);
@@ -111,7 +113,7 @@ extern "C" void mrrr_default_options(mrrr_options_t* o) {
     o->perturb_xi = 8.0;
     o->seed = 0x5eed5eedull;
     o->max_rqi = 10;
-    o->max_shift_tries = 8;
+    o->max_shift_tries = 16;
     o->max_depth = 64;
     o->workers = 0;
     o->slice_min = 2;
@@ -257,6 +259,8 @@ void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int worker
     P.sign_conv = o.sign_convention;
     P.nworkers = workers;
     P.timeout_ticks = (uint64_t)std::max(1.0, o.timeout_s * wall_khz * 1000.0);
+    P.trace = (o.trace && o.trace_cap > 0) ? static_cast<TraceRec*>(o.trace) : nullptr;
+    P.trace_cap = P.trace ? o.trace_cap : 0;
 }
 
 int check_options(const mrrr_options_t& o) {
@@ -265,6 +269,7 @@ int check_options(const mrrr_options_t& o) {
     if (!(o.perturb_xi >= 0.0 && o.perturb_xi < 1e6)) return 1;
     if (o.max_rqi < 0 || o.max_shift_tries < 1 || o.max_depth < 1) return 1;
     if (!(o.timeout_s > 0.0)) return 1;
+    if (o.trace_cap < 0) return 1;
     return 0;
 }
 
@@ -272,7 +277,7 @@ Sizes base_sizes(int64_t rows, int64_t nprob, int64_t kwork, int64_t nmax, doubl
     Sizes sz;
     sz.rows = rows;
     sz.nprob = nprob;
-    sz.max_nodes = rows + 2 * nprob + 1024;
+    sz.max_nodes = (int64_t)((double)(rows + 2 * nprob + 1024) * std::max(1.0, arena_scale));
     sz.qcap[kQRefine] = (uint64_t)std::max<int64_t>(65536, 2 * rows + 1024);
     sz.qcap[kQCluster] = (uint64_t)std::max<int64_t>(16384, rows + 1024);
     sz.qcap[kQSingle] = (uint64_t)std::max<int64_t>(16384, rows + 1024);
@@ -280,7 +285,7 @@ Sizes base_sizes(int64_t rows, int64_t nprob, int64_t kwork, int64_t nmax, doubl
     // D and L); start from a few hundred nodes of the largest block size
     const double nodes = std::min<double>((double)kwork + 2.0 * nprob, 256.0 + (double)kwork / 8.0);
     double a = 4.0 * (double)nmax * std::max(nodes, 8.0 * nprob) * std::max(arena_scale, 1e-3);
-    const double cap = 4.0 * (double)nmax * ((double)kwork + 2.0 * nprob + 8.0);
+    const double cap = 4.0 * (double)nmax * ((double)kwork + 2.0 * nprob + 8.0) * std::max(1.0, arena_scale);
     if (a > cap) a = cap;
     sz.arena = (uint64_t)std::max(a, 4.0 * (double)nmax + 64.0);
     return sz;

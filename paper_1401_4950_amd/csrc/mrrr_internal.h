@@ -99,6 +99,14 @@ struct Ctl {
     int64_t slist_top;
     int64_t n_nodes, largest_cluster, n_unverified, n_fallback, n_nan;
     int64_t qd_steps, n_tasks, n_single, n_rqi, n_blocks;
+    int64_t trace_top;
+};
+
+struct TraceRec {       // mirrors mrrr_trace_t
+    int32_t type, worker, node, depth, a, b;
+    int64_t t0, t1;
+    double x0, x1;
+    int32_t flags, child;
 };
 
 struct Params {
@@ -133,6 +141,8 @@ struct Params {
     uint64_t seed;
     int32_t max_rqi, max_tries, max_depth, slice_min, slice_max, sign_conv;
     uint64_t timeout_ticks;
+    TraceRec* trace;
+    int64_t trace_cap;
 };
 
 }  // namespace mrrr

@@ -122,45 +122,61 @@ struct Shared {
     Task task;
     int32_t ibc[8];
     double dbc[8];
+    // what the finished task reports to the trace: depth, flags, child, x0, x1
+    int32_t info_i[4];
+    double info_d[2];
 };
 
-// Rows [base, base + 64) of an N-representation (D, L): stage D, D*L and
-// D*L*L (the derived data that all lanes share).
-DEV void load_rep_tile(Shared& S, const double* D, const double* L, int64_t base, int64_t n) {
-    const int l = lane_id();
-    const int64_t r = base + l;
-    double dv = 0.0, dl = 0.0, dll = 0.0;
+// Rows [base, base + 64) of an N-representation (D, L): each lane fetches one
+// row (rep_fetch, issued one tile ahead so the loads overlap the previous
+// tile's arithmetic) and stages D, D*L and D*L*L in LDS (rep_commit) -- the
+// derived data that all lanes share.
+struct RepRow {
+    double d, l;
+};
+
+DEV RepRow rep_fetch(const double* D, const double* L, int64_t base, int64_t n) {
+    const int64_t r = base + lane_id();
+    RepRow f;
+    f.d = 0.0;
+    f.l = 0.0;
     if (r < n) {
-        dv = D[r];
-        if (r < n - 1) {
-            const double lv = L[r];
-            dl = dv * lv;
-            dll = dl * lv;
-        }
+        f.d = D[r];
+        if (r < n - 1) f.l = L[r];
     }
+    return f;
+}
+
+DEV void rep_commit(Shared& S, const RepRow& f) {
+    const int l = lane_id();
+    const double dl = f.d * f.l;
     __syncthreads();
-    S.ta[l] = dv;
+    S.ta[l] = f.d;
     S.tb[l] = dl;
-    S.tc[l] = dll;
+    S.tc[l] = dl * f.l;
     __syncthreads();
 }
 
-// Rows of T: alpha_i in ta, beta_{i-1}^2 in tb (row i couples to row i-1).
-DEV void load_T_tile(Shared& S, const double* d, const double* e, int64_t base, int64_t n) {
-    const int l = lane_id();
-    const int64_t r = base + l;
-    double a = 0.0, b2 = 0.0, b = 0.0;
+// Rows of T: alpha_i in ta, beta_{i-1}^2 in tb, beta_{i-1} in tc (row i
+// couples to row i-1).
+DEV RepRow T_fetch(const double* d, const double* e, int64_t base, int64_t n) {
+    const int64_t r = base + lane_id();
+    RepRow f;
+    f.d = 0.0;
+    f.l = 0.0;
     if (r < n) {
-        a = d[r];
-        if (r >= 1) {
-            b = e[r - 1];
-            b2 = b * b;
-        }
+        f.d = d[r];
+        if (r >= 1) f.l = e[r - 1];
     }
+    return f;
+}
+
+DEV void T_commit(Shared& S, const RepRow& f) {
+    const int l = lane_id();
     __syncthreads();
-    S.ta[l] = a;
-    S.tb[l] = b2;
-    S.tc[l] = b;
+    S.ta[l] = f.d;
+    S.tb[l] = f.l * f.l;
+    S.tc[l] = f.l;
     __syncthreads();
 }
 
@@ -170,8 +186,10 @@ DEV void load_T_tile(Shared& S, const double* d, const double* e, int64_t base, 
 DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, double sigma) {
     double s = -sigma;
     int cnt = 0;
+    RepRow f = rep_fetch(D, L, 0, n);
     for (int64_t base = 0; base < n; base += kTile) {
-        load_rep_tile(S, D, L, base, n);
+        rep_commit(S, f);
+        if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         if (lim == kTile) {
 #pragma unroll 8
@@ -196,8 +214,10 @@ DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, dou
 DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, double sigma) {
     double piv = 1.0;
     int cnt = 0;
+    RepRow f = T_fetch(d, e, 0, n);
     for (int64_t base = 0; base < n; base += kTile) {
-        load_T_tile(S, d, e, base, n);
+        T_commit(S, f);
+        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
@@ -347,12 +367,18 @@ DEV void refine_members(Shared& S, const Params& P, const double* D, const doubl
                 if (tstar < Lg) { nhi = s_hi; nf |= 2; }
                 if (tstar > 0) { nlo = s_lo; nf |= 1; }
             } else {
+                // a bracket end that fails its count is moved outward by a
+                // step that quadruples with every failure (bits 2.. of the
+                // flag count them), so any misplaced bracket is recovered in
+                // a few dozen passes
                 const double mx = fmax(fabs(lo), fabs(hi));
-                const double wid = fmax(fmax(w, 4.0 * kEps * mx), 4.0 * kSafmin);
+                const int fails = (fm >> 2) & 63;
+                const double wid = ldexp(fmax(fmax(w, 4.0 * kEps * mx), 4.0 * kSafmin), 2 * fails);
                 if (lo_good) nf |= 1;
                 if (hi_good) nf |= 2;
                 if (lo_bad) { nlo = lo - wid; nhi = lo; nf = (nf & ~1) | 2; }
                 else if (hi_bad) { nhi = hi + wid; nlo = hi; nf = (nf & ~2) | 1; }
+                if (lo_bad || hi_bad) nf = (nf & 3) | (((fails < 63 ? fails + 1 : 63)) << 2);
             }
             S.m_lo[m] = nlo;
             S.m_hi[m] = nhi;
@@ -395,8 +421,10 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
     // ---- forward: dstqds with checkpoints of (s, h)
     double s = -lam, h = 1.0, dplast = 0.0;
     int cnt = 0;
+    RepRow f = rep_fetch(D, L, 0, n);
     for (int64_t base = 0; base < n; base += kTile) {
-        load_rep_tile(S, D, L, base, n);
+        rep_commit(S, f);
+        if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
@@ -423,8 +451,10 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
     double gam_r = dplast, g_r = 1.0;
     if (live) ck.at(cl, 2) = p;
     const int64_t last_tile = ((n - 1) / kTile) * kTile;
+    RepRow fb_ = rep_fetch(D, L, last_tile, n);
     for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
-        load_rep_tile(S, D, L, tb, n);
+        rep_commit(S, fb_);
+        if (tb - kTile >= 0) fb_ = rep_fetch(D, L, tb - kTile, n);
         const int64_t cfirst = tb / kCkb;
         const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
         for (int64_t c = clast; c >= cfirst; --c) {
@@ -501,8 +531,10 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
     if (live && write) zcol[r] = scale;
     // ---- upward: rows r+1 .. n-1
     double zc = 1.0, zm1 = 0.0, zr1 = 0.0;   // z_i, z_{i-1}, saved z_{r+1}
+    RepRow fu = rep_fetch(D, L, 0, n);
     for (int64_t tb = 0; tb < n; tb += kTile) {
-        load_rep_tile(S, D, L, tb, n);
+        rep_commit(S, fu);
+        if (tb + kTile < n) fu = rep_fetch(D, L, tb + kTile, n);
         const int64_t cfirst = tb / kCkb;
         const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
         for (int64_t c = cfirst; c <= clast; ++c) {
@@ -550,8 +582,10 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
     zc = 1.0;                // z_{i+1}
     double zp2 = zr1;        // z_{i+2}
     const int64_t last_tile = ((n - 1) / kTile) * kTile;
+    RepRow fb_ = rep_fetch(D, L, last_tile, n);
     for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
-        load_rep_tile(S, D, L, tb, n);
+        rep_commit(S, fb_);
+        if (tb - kTile >= 0) fb_ = rep_fetch(D, L, tb - kTile, n);
         const int64_t cfirst = tb / kCkb;
         const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
         for (int64_t c = clast; c >= cfirst; --c) {
@@ -605,14 +639,19 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
 // pos, pos + 1 when it holds that producer's task, pos + cap once consumed.
 
 DEV bool try_pop(const Params& P, int q, Task* out) {   // one lane
+    // Polling uses relaxed loads only: an acquire at agent scope invalidates
+    // caches, and idle workers poll often.  The acquire fence follows a
+    // successful claim.
     const uint64_t cap = P.qcap[q];
     for (int spin = 0; spin < 64; ++spin) {
         uint64_t pos = __hip_atomic_load(&P.ctl->head[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t cell = pos % cap;
-        const uint64_t sq = ld_acq64(&P.seq[q][cell]);
+        const uint64_t sq = __hip_atomic_load(&P.seq[q][cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (sq == pos + 1) {
             if (__hip_atomic_compare_exchange_strong(&P.ctl->head[q], &pos, pos + 1, __ATOMIC_RELAXED,
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                (void)ld_acq64(&P.seq[q][cell]);
                 *out = P.q[q][cell];
                 st_rel64(&P.seq[q][cell], pos + cap);
                 return true;
@@ -731,8 +770,10 @@ DEV FacOut dstqds(Shared& S, const double* D, const double* L, int64_t n, double
                   double* Dp, double* Lp) {
     double s = -tau, gmax = 0.0;
     int ok = 1;
+    RepRow f = rep_fetch(D, L, 0, n);
     for (int64_t base = 0; base < n; base += kTile) {
-        load_rep_tile(S, D, L, base, n);
+        rep_commit(S, f);
+        if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
@@ -761,8 +802,10 @@ DEV FacOut factor_T(Shared& S, const double* d, const double* e, int64_t n, doub
                     bool act, double* Dd, double* Ld) {
     double dprev = 1.0, gmax = 0.0;
     int ok = 1;
+    RepRow f = T_fetch(d, e, 0, n);
     for (int64_t base = 0; base < n; base += kTile) {
-        load_T_tile(S, d, e, base, n);
+        T_commit(S, f);
+        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
@@ -1032,6 +1075,11 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         P.hi[sb + j] = rhi;
         P.vflag[sb + j] = 3;
     }
+    if (l == 0) {
+        S.info_i[2] = id;
+        S.info_d[0] = mu;
+        S.info_d[1] = spdiam;
+    }
     add_stat(&P.ctl->n_nodes, 1);
     push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull);
 }
@@ -1069,7 +1117,7 @@ DEV void task_refine(Shared& S, const Params& P, int node_id, int a, int braw, i
     C.slot_base = sb;
     C.publish = true;
     refine_members(S, P, D, L, n, M, C, steps);
-    if (l < M) P.vflag[S.m_slot[l]] = (uint8_t)S.m_flag[l];
+    if (l < M) P.vflag[S.m_slot[l]] = (uint8_t)(S.m_flag[l] & 3);
     if (mode == kModeFull && !P.jobz && l < M) {
         // eigenvalues only: the root's bisection result is final
         const int j = S.m_j[l];
@@ -1119,6 +1167,9 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     C.nb = -1;
     C.slot_base = sb;
     C.publish = true;
+#ifdef MRRR_DEBUG_TRACE
+    const double dbg_lo_in = ld_rlx_d(P.lo + sb + p), dbg_hi_in = ld_rlx_d(P.hi + sb + p);
+#endif
     refine_members(S, P, D, L, n, 2, C, steps);
     const double lo_p = S.m_lo[0], hi_p = S.m_hi[0];
     const double lo_q = S.m_lo[1], hi_q = S.m_hi[1];
@@ -1131,33 +1182,63 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (off < 0) return;
     double* C0 = P.arena + off;
     double* C1 = P.arena + off + 2 * n;
-    double taul = lo_p - 100.0 * kEps * fabs(lo_p);
-    double taur = hi_q + 100.0 * kEps * fabs(hi_q);
+    // All back-off levels of Alg. 3.8 are factorised at once: lane 2t uses
+    // tau_l(t) and lane 2t+1 tau_r(t).  Level 0 sits 100 eps |lambda|
+    // outside the cluster; levels 1..T-1 back off geometrically from
+    // 100 eps |lambda| + eps spdiam up to a quarter of the gap to the nearest
+    // eigenvalue outside the cluster on that side, so that no level moves the
+    // shift past the cluster's neighbours (which would keep the cluster from
+    // being broken).  The selection below is the algorithm's sequential rule:
+    // the first level whose better candidate passes the growth test wins;
+    // otherwise the least growth seen.  Only level 0 stores its pair.
     const double spd = par.spdiam;
-    const double thresh = 8.0 * spd;
+    const double thresh = 8.0 * spd;    // ||D+|| = O(spdiam): accept at once
+    const int T = P.max_tries < 32 ? P.max_tries : 32;
+    const int tt = l >> 1, side = l & 1;
+    const double tau_l0 = lo_p - 100.0 * kEps * fabs(lo_p);
+    const double tau_r0 = hi_q + 100.0 * kEps * fabs(hi_q);
+    double mytau = side ? tau_r0 : tau_l0;
+    // the gap between the end member and its inner neighbour: the child can
+    // split the end member off only if the shift stays within about
+    // gap / gaptol of it
+    const double gin_l = fmax(ld_rlx_d(P.lo + sb + p + 1) - hi_p, 0.0);
+    const double gin_r = fmax(lo_q - ld_rlx_d(P.hi + sb + q - 1), 0.0);
+    if (tt >= 1 && T >= 2) {
+        // relative steps only: an absolute floor (say eps * spdiam) would stop
+        // a deep node, whose eigenvalues are tiny, from ever getting closer
+        const double dmin = fmax(100.0 * kEps * (side ? fmax(fabs(lo_q), fabs(hi_q))
+                                                       : fmax(fabs(lo_p), fabs(hi_p))),
+                                 64.0 * kSafmin);
+        const double g = side ? rgap : lgap;
+        const double gin = side ? gin_r : gin_l;
+        const double dmax = fmax(dmin, fmin(0.25 * fmin(__builtin_isfinite(g) ? g : spd, spd),
+                                             gin / (2.0 * P.gaptol)));
+        const double frac = (T > 2) ? (double)(tt - 1) / (double)(T - 2) : 0.0;
+        const double del = dmin * pow(dmax / dmin, frac);
+        mytau = side ? tau_r0 + del : tau_l0 - del;
+    }
+    const FacOut f = dstqds(S, D, L, n, mytau, tt == 0, side ? C1 : C0, (side ? C1 : C0) + n);
+    steps += 2 * n * T;
     double best = __builtin_inf(), best_tau = 0.0;
     int chosen = -1;
-    double tau = 0.0;
-    for (int tr = 0; tr < P.max_tries; ++tr) {
-        const double tl = (l == 0) ? taul : taur;
-        const FacOut f = dstqds(S, D, L, n, tl, l < 2, (l == 0) ? C0 : C1, ((l == 0) ? C0 : C1) + n);
-        steps += 2 * n;
-        const int ok0 = __shfl(f.ok, 0), ok1 = __shfl(f.ok, 1);
-        const double g0 = __shfl(f.growth, 0), g1 = __shfl(f.growth, 1);
+    double tau = 0.0, chosen_growth = 0.0;
+    for (int t = 0; t < T; ++t) {
+        const int ok0 = __shfl(f.ok, 2 * t), ok1 = __shfl(f.ok, 2 * t + 1);
+        const double g0 = __shfl(f.growth, 2 * t), g1 = __shfl(f.growth, 2 * t + 1);
+        const double t0 = __shfl(mytau, 2 * t), t1 = __shfl(mytau, 2 * t + 1);
         int pick = -1;
         if (ok0 && ok1) pick = (g1 < g0) ? 1 : 0;
         else if (ok0) pick = 0;
         else if (ok1) pick = 1;
-        if (pick >= 0) {
-            const double g = pick ? g1 : g0;
-            const double tp = pick ? taur : taul;
-            if (g < best) { best = g; best_tau = tp; }
-            if (g <= thresh) { chosen = pick; tau = tp; break; }
+        if (pick < 0) continue;
+        const double g = pick ? g1 : g0;
+        const double tp = pick ? t1 : t0;
+        if (g < best) { best = g; best_tau = tp; }
+        if (g <= thresh && chosen < 0) {
+            chosen = (t == 0) ? pick : 2;   // 2: not stored yet
+            tau = tp;
+            chosen_growth = g;
         }
-        const double dl = ldexp(100.0 * kEps * fabs(lo_p) + kEps * spd, tr);
-        const double dr = ldexp(100.0 * kEps * fabs(hi_q) + kEps * spd, tr);
-        taul -= dl;
-        taur += dr;
     }
     int unverified = 0;
     if (chosen < 0) {
@@ -1166,11 +1247,15 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
             return;
         }
         // no candidate passed: the least element growth (Alg. 3.8, last line)
-        dstqds(S, D, L, n, best_tau, l == 0, C0, C0 + n);
+        chosen = 2;
+        tau = best_tau;
+        chosen_growth = best;
+        unverified = 1;
+    }
+    if (chosen == 2) {
+        dstqds(S, D, L, n, tau, l == 0, C0, C0 + n);
         steps += n;
         chosen = 0;
-        tau = best_tau;
-        unverified = 1;
     }
     const int id = new_node(P);
     if (id < 0) return;
@@ -1201,6 +1286,19 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         st_rlx_d(P.lo + slot, grow_lo(grow_lo(lo, nu) - tau, nu));
         st_rlx_d(P.hi + slot, grow_hi(grow_hi(hi, nu) - tau, nu));
         P.vflag[slot] = 0;
+    }
+    if (l == 0) {
+        S.info_i[0] = par.depth;
+        S.info_i[1] = unverified;
+        S.info_i[2] = id;
+        S.info_d[0] = tau;
+        S.info_d[1] = chosen_growth;
+#ifdef MRRR_DEBUG_TRACE
+        S.info_d[0] = lo_p;
+        S.info_d[1] = dbg_lo_in;
+        S.info_i[1] = (int)(S.m_flag[0] & 3);
+        (void)dbg_hi_in;
+#endif
     }
     add_stat(&P.ctl->n_nodes, 1);
     add_stat(&P.ctl->n_unverified, unverified);
@@ -1336,12 +1434,13 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_tree_kernel(Params P) {
     for (;;) {
         if (l == 0) {
             int status = 0;
+            int nap = 1;
             for (;;) {
                 if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { status = 2; break; }
                 bool got = false;
                 for (int qq = 0; qq < kNumQ && !got; ++qq) got = try_pop(P, qq, &S.task);
                 if (got) { status = 1; break; }
-                if (__hip_atomic_load(&P.ctl->pending, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) { status = 2; break; }
+                if (__hip_atomic_load(&P.ctl->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) { status = 2; break; }
                 if (wall_clock64() - t0 > P.timeout_ticks) {
                     int32_t expect = 0;
                     __hip_atomic_compare_exchange_strong(&P.ctl->error, &expect, (int32_t)kErrTimeout,
@@ -1349,7 +1448,9 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_tree_kernel(Params P) {
                     status = 2;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                // back off while the queues are empty (up to ~4 us between polls)
+                for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(127);
+                if (nap < 8) nap *= 2;
             }
             S.ibc[0] = status;
         }
@@ -1359,6 +1460,12 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_tree_kernel(Params P) {
         __syncthreads();
         if (status != 1) break;
         __threadfence();
+        const uint64_t ts = wall_clock64();
+        if (l == 0) {
+            S.info_i[0] = 0; S.info_i[1] = 0; S.info_i[2] = -1; S.info_i[3] = 0;
+            S.info_d[0] = 0.0; S.info_d[1] = 0.0;
+        }
+        __syncthreads();
         switch (tk.type) {
             case kTaskRoot: task_root(S, P, tk.node, steps); break;
             case kTaskRefine: task_refine(S, P, tk.node, tk.a, tk.b, steps); break;
@@ -1368,6 +1475,26 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_tree_kernel(Params P) {
         }
         __threadfence();
         __syncthreads();
+        if (P.trace && l == 0) {
+            const int64_t k = __hip_atomic_fetch_add(&P.ctl->trace_top, (int64_t)1, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            if (k < P.trace_cap) {
+                TraceRec r;
+                r.type = tk.type;
+                r.worker = (int32_t)blockIdx.x;
+                r.node = tk.node;
+                r.depth = S.info_i[0];
+                r.a = tk.a;
+                r.b = tk.b;
+                r.t0 = (int64_t)ts;
+                r.t1 = (int64_t)wall_clock64();
+                r.x0 = S.info_d[0];
+                r.x1 = S.info_d[1];
+                r.flags = S.info_i[1];
+                r.child = S.info_i[2];
+                P.trace[k] = r;
+            }
+        }
         if (l == 0) __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)-1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         ++ntask;
     }

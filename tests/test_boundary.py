@@ -32,7 +32,7 @@ def test_defaults_and_status_strings(lib):
     o = _lib.default_options()
     assert o.jobz == 1 and o.sign_convention == 1
     assert o.gaptol == 1e-3 and o.rtol_class == 1e-5
-    assert o.perturb_xi == 8.0 and o.max_rqi == 10 and o.max_shift_tries == 8
+    assert o.perturb_xi == 8.0 and o.max_rqi == 10 and o.max_shift_tries == 16
     for code in range(0, 8):
         assert lib.mrrr_status_string(code)
     assert b"invalid" in lib.mrrr_status_string(-3)
