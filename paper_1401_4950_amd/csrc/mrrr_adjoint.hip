@@ -37,8 +37,9 @@ constexpr int kBM = 64, kBN = 64, kBK = 16;
 // C(i, j) = sum_k A(i, k) B(k, j) over one 64 x 64 tile; A(i, k) =
 // A[i*sai + k*sak], B(k, j) = B[k*sbk + j*sbj].  256 threads = 4 waves in a
 // 2 x 2 arrangement, each wave 32 x 32 = 2 x 2 MFMA tiles of 16 x 16.
-// Lane layout of v_mfma_f64_16x16x4f64: A(i, k) from lane i + 16 k, B(k, j)
-// from lane j + 16 k, and lane l holds C(4 (l / 16) + r, l % 16), r = 0..3.
+// Lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950): A(i, k) from
+// lane i + 16 k, B(k, j) from lane j + 16 k, and result register r of lane l
+// holds C(4 r + l / 16, l % 16), r = 0..3.
 template <class Epi>
 __device__ __forceinline__ void mfma_tile(const double* __restrict__ A, int64_t sai, int64_t sak,
                                           const double* __restrict__ B, int64_t sbk, int64_t sbj,
@@ -115,7 +116,7 @@ extern "C" __global__ __launch_bounds__(256) void mrrr_adj_form_m(const AdjProb*
                       for (int b = 0; b < 2; ++b)
 #pragma unroll
                           for (int r = 0; r < 4; ++r) {
-                              const int64_t i = ib + a * 16 + 4 * (lane >> 4) + r;
+                              const int64_t i = ib + a * 16 + 4 * r + (lane >> 4);
                               const int64_t j = jb + b * 16 + (lane & 15);
                               if (i < n && j < n) {
                                   double v;
@@ -157,7 +158,7 @@ extern "C" __global__ __launch_bounds__(256) void mrrr_adj_reduce(const AdjProb*
                   for (int a = 0; a < 2; ++a)
 #pragma unroll
                       for (int r = 0; r < 4; ++r) {
-                          const int64_t i = ib + a * 16 + 4 * (lane >> 4) + r;
+                          const int64_t i = ib + a * 16 + 4 * r + (lane >> 4);
                           double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
                           for (int b = 0; b < 2; ++b) {

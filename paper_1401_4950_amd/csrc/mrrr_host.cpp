@@ -53,11 +53,11 @@ struct DevBuf {
 };
 
 struct Workspace {
-    DevBuf probs, blocks, nodes, q[kNumQ], seq[kNumQ], lo, hi, gap, vflag, slist, arena, ck, colbuf, perm, ctl;
+    DevBuf probs, blocks, nodes, q[kNumQ], seq[kNumQ], lo, hi, gap, lo0, hi0, vflag, slist, arena, ck, colbuf, perm, ctl;
     void release() {
         probs.release(); blocks.release(); nodes.release();
         for (int i = 0; i < kNumQ; ++i) { q[i].release(); seq[i].release(); }
-        lo.release(); hi.release(); gap.release(); vflag.release(); slist.release();
+        lo.release(); hi.release(); gap.release(); lo0.release(); hi0.release(); vflag.release(); slist.release();
         arena.release(); ck.release(); colbuf.release(); perm.release(); ctl.release();
     }
 };
@@ -212,6 +212,8 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     ENS(ws.lo, sizeof(double) * r);
     ENS(ws.hi, sizeof(double) * r);
     ENS(ws.gap, sizeof(double) * r);
+    ENS(ws.lo0, sizeof(double) * r);
+    ENS(ws.hi0, sizeof(double) * r);
     ENS(ws.vflag, r);
     ENS(ws.slist, sizeof(int32_t) * r);
     ENS(ws.arena, sizeof(double) * sz.arena);
@@ -232,6 +234,8 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     P.lo = ws.lo.as<double>();
     P.hi = ws.hi.as<double>();
     P.gap = ws.gap.as<double>();
+    P.lo0 = ws.lo0.as<double>();
+    P.hi0 = ws.hi0.as<double>();
     P.vflag = ws.vflag.as<uint8_t>();
     P.slist = ws.slist.as<int32_t>();
     P.slist_cap = sz.rows;

@@ -127,6 +127,8 @@ struct Params {
     double* lo;           // per slot bracket, in the frame of its current node
     double* hi;
     double* gap;          // per slot absolute gap (singletons)
+    double* lo0;          // per slot bracket as the current node received it
+    double* hi0;          //   (a deterministic snapshot for neighbour tests)
     uint8_t* vflag;       // per slot: bit0 lo verified, bit1 hi verified
     int32_t* slist;       // singleton lists
     int64_t slist_cap;

@@ -307,11 +307,18 @@ DEV void refine_members(Shared& S, const Params& P, const double* D, const doubl
             const double lo = S.m_lo[l], hi = S.m_hi[l];
             bool conv = bracket_done(P, C.mode, lo, hi);
             if (!conv && C.mode == kModeClass && C.na >= 0) {
+                // neighbours inside the slice: their current brackets (LDS);
+                // outside: the brackets the node started with.  Both are
+                // fixed by the slice's own inputs, so the outcome does not
+                // depend on how other slices are scheduled.
                 const int j = S.m_j[l];
                 if (j > C.na && j < C.nb) {
                     const int64_t sl = C.slot_base + j;
-                    const double llo = ld_rlx_d(P.lo + sl - 1), lhi = ld_rlx_d(P.hi + sl - 1);
-                    const double rlo = ld_rlx_d(P.lo + sl + 1), rhi = ld_rlx_d(P.hi + sl + 1);
+                    double llo, lhi, rlo, rhi;
+                    if (l > 0) { llo = S.m_lo[l - 1]; lhi = S.m_hi[l - 1]; }
+                    else { llo = P.lo0[sl - 1]; lhi = P.hi0[sl - 1]; }
+                    if (l + 1 < M) { rlo = S.m_lo[l + 1]; rhi = S.m_hi[l + 1]; }
+                    else { rlo = P.lo0[sl + 1]; rhi = P.hi0[sl + 1]; }
                     conv = surely_clustered(llo, lhi, lo, hi, P.gaptol) &&
                            surely_clustered(lo, hi, rlo, rhi, P.gaptol);
                 }
@@ -870,9 +877,15 @@ DEV void classify(Shared& S, const Params& P, int node_id) {
         set_error(P, kErrNoMem);
         return;
     }
-    // pass 2: write the singleton list, gaps, and enqueue clusters
+    // pass 2: write the singleton list, gaps, and enqueue clusters.  A
+    // cluster pushed in one chunk may be taken at once, and its task rewrites
+    // its members' brackets in the child's coordinates; the one member of an
+    // earlier chunk that a later chunk needs (its left neighbour) is therefore
+    // carried in registers instead of being read again.
     int pos = 0;
     int open = -1;           // start of the cluster being scanned
+    double open_lg = 0.0;    // its gap to the left neighbour
+    double carry_lo = 0.0, carry_hi = 0.0;
     int64_t largest = 0;
     int ncl = 0, nunv = 0;
     for (int base = a; base <= b; base += kWave) {
@@ -885,8 +898,13 @@ DEV void classify(Shared& S, const Params& P, int node_id) {
             sbf = (j == a);
             saf = (j == b);
             if (!sbf) {
-                llo = ld_rlx_d(P.lo + sb + j - 1);
-                lhi = ld_rlx_d(P.hi + sb + j - 1);
+                if (l == 0) {
+                    llo = carry_lo;
+                    lhi = carry_hi;
+                } else {
+                    llo = ld_rlx_d(P.lo + sb + j - 1);
+                    lhi = ld_rlx_d(P.hi + sb + j - 1);
+                }
                 sbf = pair_split(llo, lhi, lo, hi, P.gaptol);
             }
             if (!saf) {
@@ -899,14 +917,16 @@ DEV void classify(Shared& S, const Params& P, int node_id) {
                 nunv += 1;
             }
         }
+        carry_lo = __shfl(lo, kWave - 1);
+        carry_hi = __shfl(hi, kWave - 1);
         const bool in = (j <= b);
         const bool single = in && sbf && saf && j >= blk.w0 && j <= blk.w1;
         const uint64_t sm = __ballot(single);
+        const double lg = (j == a) ? nd.lgap : (lo - lhi);
+        const double rg = (j == b) ? nd.rgap : (rlo - hi);
         if (single) {
             const int k = pos + __popcll(sm & ((1ull << l) - 1ull));
             P.slist[off + k] = (int32_t)(sb + j);
-            const double lg = (j == a) ? nd.lgap : (lo - lhi);
-            const double rg = (j == b) ? nd.rgap : (rlo - hi);
             P.gap[sb + j] = fmin(lg, rg);
         }
         pos += __popcll(sm);
@@ -918,14 +938,22 @@ DEV void classify(Shared& S, const Params& P, int node_id) {
             const int t = __ffsll((unsigned long long)ev) - 1;
             ev &= ev - 1ull;
             const int jj = base + t;
+            const double lg_t = __shfl(lg, t), rg_t = __shfl(rg, t);
             if ((starts >> t) & 1ull) {
                 open = jj;
+                open_lg = lg_t;
             } else if (open >= 0) {
                 const int p = open, q = jj;
                 open = -1;
                 if ((int64_t)(q - p + 1) > largest) largest = q - p + 1;
                 if (q >= blk.w0 && p <= blk.w1) {
                     ++ncl;
+                    // the cluster's gaps to its outside neighbours travel in
+                    // gap[] at its end slots (published by the push)
+                    if (l == 0) {
+                        P.gap[sb + p] = open_lg;
+                        P.gap[sb + q] = rg_t;
+                    }
                     Task tk;
                     tk.type = kTaskCluster;
                     tk.node = node_id;
@@ -1073,6 +1101,8 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     for (int64_t j = blk.k0 + l; j <= blk.k1; j += kWave) {
         P.lo[sb + j] = rlo;
         P.hi[sb + j] = rhi;
+        P.lo0[sb + j] = rlo;
+        P.hi0[sb + j] = rhi;
         P.vflag[sb + j] = 3;
     }
     if (l == 0) {
@@ -1173,9 +1203,11 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     refine_members(S, P, D, L, n, 2, C, steps);
     const double lo_p = S.m_lo[0], hi_p = S.m_hi[0];
     const double lo_q = S.m_lo[1], hi_q = S.m_hi[1];
-    // gaps to the neighbours outside the cluster (shift invariant)
-    const double lgap = (p > par.a) ? lo_p - ld_rlx_d(P.hi + sb + p - 1) : par.lgap;
-    const double rgap = (q < par.b) ? ld_rlx_d(P.lo + sb + q + 1) - hi_q : par.rgap;
+    // gaps to the neighbours outside the cluster (shift invariant), as the
+    // parent's classification measured them: the neighbours' brackets may be
+    // rewritten meanwhile by their own tasks
+    const double lgap = ld_rlx_d(P.gap + sb + p);
+    const double rgap = ld_rlx_d(P.gap + sb + q);
     // 2. shifts just outside both ends; keep the candidate with the smaller
     //    element growth; back off while the growth is too large (Alg. 3.8)
     const int64_t off = arena_alloc(P, 4 * n);
@@ -1283,8 +1315,12 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         double lo = ld_rlx_d(P.lo + slot), hi = ld_rlx_d(P.hi + slot);
         if (j == p) { lo = lo_p; hi = hi_p; }
         if (j == q) { lo = lo_q; hi = hi_q; }
-        st_rlx_d(P.lo + slot, grow_lo(grow_lo(lo, nu) - tau, nu));
-        st_rlx_d(P.hi + slot, grow_hi(grow_hi(hi, nu) - tau, nu));
+        const double clo = grow_lo(grow_lo(lo, nu) - tau, nu);
+        const double chi = grow_hi(grow_hi(hi, nu) - tau, nu);
+        st_rlx_d(P.lo + slot, clo);
+        st_rlx_d(P.hi + slot, chi);
+        P.lo0[slot] = clo;
+        P.hi0[slot] = chi;
         P.vflag[slot] = 0;
     }
     if (l == 0) {

@@ -1,0 +1,237 @@
+"""Parity of the HIP MRRR path (through the C ABI) against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import tridiag_inputs as ti
+from oracle import metrics as M
+
+pytestmark = pytest.mark.gpu
+
+from _gpu_util import EPS, check_pairs, gpu_residual_orth, gpu_solve, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+# sizes that straddle the 64-row tiles and 16-row checkpoint blocks
+SIZES = [1, 2, 3, 4, 5, 8, 15, 16, 17, 31, 63, 64, 65, 100, 127, 128, 129, 255, 257, 333]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_random_sizes(orc, n):
+    d, e = ti.random_uniform(n, n)
+    w, Z = gpu_solve(d, e)
+    wo, Zo = orc.solve(d, e)
+    check_pairs(d, e, w, Z, wo, Zo)
+
+
+@pytest.mark.parametrize("fam", ["random", "121", "clement", "glued_wilkinson", "hermite", "legendre"])
+def test_families_n1000(orc, fam):
+    for seed in (0, 1, 2) if fam == "random" else (0,):
+        d, e = ti.family(fam, 1000, seed)
+        w, Z = gpu_solve(d, e)
+        wo, Zo = orc.solve(d, e)
+        check_pairs(d, e, w, Z, wo, Zo)
+
+
+def test_wilkinson_single_block(orc):
+    d, e = ti.wilkinson_plus(201)
+    w, Z = gpu_solve(d, e)
+    wo, Zo = orc.solve(d, e)
+    check_pairs(d, e, w, Z, wo, Zo)
+
+
+def test_config1_against_jacobi(orc):
+    """n = 1000, d, e uniform[-1, 1]: all pairs against brute-force Jacobi."""
+    d, e = ti.random_uniform(1000, 0)
+    w, Z = gpu_solve(d, e)
+    wj, V = orc.jacobi_tridiag(d, e)
+    n = 1000
+    assert np.max(np.abs(w - wj)) <= 20 * n * EPS * np.linalg.norm(orc.dense(d, e))
+    tn = M.tnorm_of(wj)
+    for (a, b) in __import__("_gpu_util").oracle_clusters(wj, tn):
+        if b - a == 1:
+            assert abs(Z[:, a] @ V[:, a]) >= 1 - 1e-9
+
+
+def test_closed_forms(orc):
+    n = 500
+    d, e = ti.one_two_one(n, -1.0)
+    w, Z = gpu_solve(d, e)
+    k = np.arange(1, n + 1)
+    lam = 2.0 - 2.0 * np.cos(np.pi * k / (n + 1))
+    assert np.max(np.abs(w - lam)) <= 4 * n * EPS * 4.0
+    S = M.sign_normalize(np.sqrt(2.0 / (n + 1)) * np.sin(np.arange(1, n + 1)[:, None] * k[None, :] * np.pi / (n + 1)))
+    assert M.subspace_sigma_min(Z, S) >= 1 - 1e-8
+    d, e = ti.clement(n)
+    w = gpu_solve(d, e, eigvals_only=True)
+    assert np.max(np.abs(w - (-(n - 1) + 2.0 * np.arange(n)))) <= 4 * n * EPS * (n - 1)
+
+
+def test_sign_convention():
+    d, e = ti.random_uniform(300, 4)
+    _, Z = gpu_solve(d, e)
+    idx = np.argmax(np.abs(Z), axis=0)
+    assert np.all(Z[idx, np.arange(Z.shape[1])] > 0)
+
+
+@pytest.mark.parametrize("il,iu", [(1, 1), (1, 50), (17, 17), (100, 250), (451, 500), (1, 500), (250, 249)])
+def test_index_ranges(orc, il, iu):
+    d, e = ti.random_uniform(500, 9)
+    w, Z = gpu_solve(d, e, select="i", select_range=(il, iu))
+    wo, Zo = orc.solve(d, e, "index", il=il, iu=iu)
+    assert len(w) == max(iu - il + 1, 0)
+    check_pairs(d, e, w, Z, wo, Zo, tnorm=M.tnorm_of(orc.solve(d, e, vectors=False)))
+
+
+def test_index_range_clustered(orc):
+    """Ranges whose ends cut clusters of 20 equal (to working precision)
+    eigenvalues: the cut part must lie in the whole cluster's span."""
+    d, e = ti.glued_wilkinson(420)
+    w_all, Z_all = orc.solve(d, e)
+    for il, iu in [(1, 30), (190, 260), (401, 420)]:
+        w, Z = gpu_solve(d, e, select="i", select_range=(il, iu))
+        wo = orc.solve(d, e, "index", il=il, iu=iu, vectors=False)
+        check_pairs(d, e, w, Z, wo, tnorm=M.tnorm_of(w_all), full=(w_all, Z_all, il - 1))
+
+
+def test_value_ranges(orc):
+    d, e = ti.random_uniform(400, 3)
+    wall = orc.solve(d, e, vectors=False)
+    tn = M.tnorm_of(wall)
+    for vl, vu in [(-0.5, 0.25), (wall[0] - 1, wall[-1] + 1), (0.5 * (wall[9] + wall[10]), 0.5 * (wall[99] + wall[100]))]:
+        w, Z = gpu_solve(d, e, select="v", select_range=(vl, vu))
+        wo, Zo = orc.solve(d, e, "value", vl=vl, vu=vu)
+        check_pairs(d, e, w, Z, wo, Zo, tnorm=tn)
+    w = gpu_solve(d, e, select="v", select_range=(10.0, 11.0), eigvals_only=True)
+    assert len(w) == 0
+
+
+def test_splitting(orc):
+    d, e = ti.random_uniform(300, 6)
+    e[49] = 0.0
+    e[50] = 0.0          # a 1x1 block at row 50
+    e[199] = 1e-300
+    w, Z = gpu_solve(d, e)
+    wo, Zo = orc.solve(d, e)
+    check_pairs(d, e, w, Z, wo, Zo)
+    # value range over the split matrix
+    w, Z = gpu_solve(d, e, select="v", select_range=(-0.3, 0.4))
+    wo, Zo = orc.solve(d, e, "value", vl=-0.3, vu=0.4)
+    check_pairs(d, e, w, Z, wo, Zo, tnorm=M.tnorm_of(orc.solve(d, e, vectors=False)))
+
+
+def test_index_range_with_split_is_refused():
+    from paper_1401_4950_amd import MrrrError
+    d, e = ti.random_uniform(100, 1)
+    e[40] = 0.0
+    with pytest.raises(MrrrError) as ex:
+        gpu_solve(d, e, select="i", select_range=(3, 10))
+    assert ex.value.code == 5
+
+
+def test_values_only_matches_vectors_run(orc):
+    d, e = ti.random_uniform(700, 8)
+    w = gpu_solve(d, e, eigvals_only=True)
+    wo = orc.solve(d, e, vectors=False)
+    assert np.max(np.abs(w - wo)) <= 4 * 700 * EPS * M.tnorm_of(wo)
+
+
+def test_bad_inputs():
+    from paper_1401_4950_amd import MrrrError
+    d, e = ti.random_uniform(50, 1)
+    d[7] = np.nan
+    with pytest.raises(MrrrError) as ex:
+        gpu_solve(d, e)
+    assert ex.value.code == -3
+    d, e = ti.random_uniform(50, 1)
+    e[3] = np.inf
+    with pytest.raises(MrrrError) as ex:
+        gpu_solve(d, e)
+    assert ex.value.code == -4
+
+
+def test_zero_and_tiny():
+    w = gpu_solve(np.zeros(0), np.zeros(0), eigvals_only=True)
+    assert len(w) == 0
+    w, Z = gpu_solve(np.array([3.5]), np.zeros(0))
+    assert w[0] == 3.5 and Z[0, 0] == 1.0
+    # diagonal matrix: every row its own block
+    d = np.array([3.0, -1.0, 2.0, 0.5])
+    w, Z = gpu_solve(d, np.zeros(3))
+    assert np.array_equal(w, np.sort(d))
+    assert np.array_equal(np.abs(Z), np.eye(4)[:, np.argsort(d)])
+
+
+def test_determinism():
+    d, e = ti.glued_wilkinson(500)
+    w1, Z1 = gpu_solve(d, e)
+    w2, Z2 = gpu_solve(d, e)
+    assert np.array_equal(w1, w2) and np.array_equal(Z1, Z2)
+
+
+def test_stats_and_trace():
+    import ctypes
+    import torch
+    import paper_1401_4950_amd as mr
+    from paper_1401_4950_amd import _lib
+    d, e = ti.one_two_one(2000)
+    cap = 100000
+    buf = torch.zeros(cap * _lib.TRACE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    mr.eigh_tridiagonal(to_dev(d), to_dev(e), options={"trace": buf.data_ptr(), "trace_cap": cap})
+    torch.cuda.synchronize()
+    st = mr.last_stats()
+    assert st["m"] == 2000 and st["n_blocks"] == 1 and st["n_tasks"] > 0 and st["qd_steps"] > 0
+    rec = np.frombuffer(buf.cpu().numpy().tobytes(), dtype=np.dtype(_lib.TRACE_FIELDS))[: st["n_tasks"]]
+    assert set(np.unique(rec["type"])) <= {1, 2, 3, 4}
+    assert (rec["type"] == 1).sum() == 1
+    assert np.all(rec["t1"] >= rec["t0"])
+    # every singleton bundle's size adds up to n
+    assert int(rec[rec["type"] == 4]["b"].sum()) == 2000
+
+
+# ------------------------------------------------------- full-size configs
+
+
+@pytest.mark.parametrize("fam", ["121", "clement", "glued_wilkinson", "random"])
+def test_config2_n20000(orc, fam):
+    """n = 20000, all pairs: sampled eigenvalues against the oracle's
+    bisection, residual of every column, orthogonality of all of Z^T Z."""
+    import torch
+    import paper_1401_4950_amd as mr
+    n = 20000
+    d, e = ti.family(fam, n, 0)
+    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e))
+    torch.cuda.synchronize()
+    idx = np.unique(np.linspace(1, n, 48).astype(int))
+    wo = np.array([orc.eigval_index(d, e, int(k)) for k in idx])
+    wh = w.cpu().numpy()
+    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
+    assert np.all(np.diff(wh) >= 0)
+    assert np.max(np.abs(wh[idx - 1] - wo)) <= 4 * n * EPS * tn
+    res, orth = gpu_residual_orth(d, e, w, Z, tn)
+    assert res <= 10 and orth <= 100, (res, orth)
+
+
+@pytest.mark.parametrize("fam", ["random", "glued_wilkinson"])
+def test_config3_subset_n50000(orc, fam):
+    import torch
+    import paper_1401_4950_amd as mr
+    n, k = 50000, 5000
+    d, e = ti.family(fam, n, 0)
+    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e), select="i", select_range=(1, k))
+    torch.cuda.synchronize()
+    assert w.shape[0] == k and Z.shape == (n, k)
+    idx = np.unique(np.linspace(1, k, 24).astype(int))
+    wo = np.array([orc.eigval_index(d, e, int(j)) for j in idx])
+    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
+    wh = w.cpu().numpy()
+    assert np.max(np.abs(wh[idx - 1] - wo)) <= 4 * n * EPS * tn
+    res, orth = gpu_residual_orth(d, e, w, Z, tn)
+    assert res <= 10 and orth <= 100, (res, orth)
