@@ -113,6 +113,9 @@ typedef struct {
     int64_t n_rqi_iters;       /* lane Rayleigh-quotient iterations */
     int64_t arena_bytes;       /* node-pool bytes used */
     double ms;                 /* device time of the solve (hipEvent), ms */
+    double tree_ms;            /* device time of the persistent tree kernel
+                                  alone (hipEvents on the handle's stream
+                                  around its launch); 0 for batched calls */
 } mrrr_stats_t;
 
 /* Creates a handle on HIP device `device`.  The handle owns a workspace that

@@ -49,7 +49,7 @@ class Stats(ctypes.Structure):
         ("n_unverified_rrr", ctypes.c_int64), ("n_bisect_fallback", ctypes.c_int64),
         ("n_nan_retry", ctypes.c_int64), ("qd_steps", ctypes.c_int64), ("n_tasks", ctypes.c_int64),
         ("n_singleton_tasks", ctypes.c_int64), ("n_rqi_iters", ctypes.c_int64),
-        ("arena_bytes", ctypes.c_int64), ("ms", ctypes.c_double),
+        ("arena_bytes", ctypes.c_int64), ("ms", ctypes.c_double), ("tree_ms", ctypes.c_double),
     ]
 
     def as_dict(self):

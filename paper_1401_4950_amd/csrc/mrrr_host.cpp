@@ -98,7 +98,7 @@ struct mrrr_handle_s {
     int occ = 0;
     double wall_khz = 100000.0;
     Workspace ws;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evt0 = nullptr, evt1 = nullptr;
     mrrr_batched_plan_s* plan = nullptr;   // most recent batched plan
     DevBuf adj;                            // backward scratch
 };
@@ -155,7 +155,10 @@ extern "C" int mrrr_create(mrrr_handle_t* h, int device) {
     int occ = 0;
     if (tree_occupancy(&occ) != hipSuccess || occ < 1) occ = 1;
     H->occ = occ;
-    if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess) {
+    if (hipEventCreate(&H->ev0) != hipSuccess || hipEventCreate(&H->ev1) != hipSuccess ||
+        hipEventCreate(&H->evt0) != hipSuccess || hipEventCreate(&H->evt1) != hipSuccess) {
+        for (hipEvent_t ev : {H->ev0, H->ev1, H->evt0, H->evt1})
+            if (ev) (void)hipEventDestroy(ev);
         delete H;
         return MRRR_EHIP;
     }
@@ -172,6 +175,8 @@ extern "C" int mrrr_destroy(mrrr_handle_t h) {
     h->adj.release();
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
+    if (h->evt0) (void)hipEventDestroy(h->evt0);
+    if (h->evt1) (void)hipEventDestroy(h->evt1);
     delete h;
     return MRRR_OK;
 }
@@ -304,7 +309,7 @@ int read_back(mrrr_handle_t h, const Params& P, Ctl* ctl_h, std::vector<Problem>
     return MRRR_OK;
 }
 
-void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms) {
+void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms, float tree_ms = 0.f) {
     if (!st) return;
     std::memset(st, 0, sizeof(*st));
     st->m = m;
@@ -321,13 +326,18 @@ void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms) {
     st->n_rqi_iters = c.n_rqi;
     st->arena_bytes = (int64_t)(c.arena_top * sizeof(double));
     st->ms = ms;
+    st->tree_ms = tree_ms;
 }
 
-hipError_t enqueue_solve(const Params& P, int64_t ncols_total, bool sign, hipStream_t s) {
+// ev_tree: optional pair of events recorded around the tree kernel
+hipError_t enqueue_solve(const Params& P, int64_t ncols_total, bool sign, hipStream_t s,
+                         hipEvent_t* ev_tree = nullptr) {
     hipError_t e;
     if ((e = launch_init(P, s)) != hipSuccess) return e;
     if ((e = launch_setup(P, s)) != hipSuccess) return e;
+    if (ev_tree && (e = hipEventRecord(ev_tree[0], s)) != hipSuccess) return e;
     if ((e = launch_tree(P, s)) != hipSuccess) return e;
+    if (ev_tree && (e = hipEventRecord(ev_tree[1], s)) != hipSuccess) return e;
     if ((e = launch_finalize(P, s)) != hipSuccess) return e;
     if (sign && P.jobz && (e = launch_sign(P, ncols_total, s)) != hipSuccess) return e;
     return hipSuccess;
@@ -402,20 +412,22 @@ extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const do
         if (hipMemcpyAsync(P.probs, &pr, sizeof(Problem), hipMemcpyHostToDevice, h->stream) != hipSuccess)
             return MRRR_EHIP;
         if (hipEventRecord(h->ev0, h->stream) != hipSuccess) return MRRR_EHIP;
-        if (enqueue_solve(P, n, o.sign_convention != 0, h->stream) != hipSuccess) return MRRR_EHIP;
+        hipEvent_t evt[2] = {h->evt0, h->evt1};
+        if (enqueue_solve(P, n, o.sign_convention != 0, h->stream, evt) != hipSuccess) return MRRR_EHIP;
         if (hipEventRecord(h->ev1, h->stream) != hipSuccess) return MRRR_EHIP;
         Ctl c{};
         std::vector<Problem> ph(1);
         if ((status = read_back(h, P, &c, &ph)) != MRRR_OK) return status;
-        float ms = 0.f;
+        float ms = 0.f, tms = 0.f;
         (void)hipEventElapsedTime(&ms, h->ev0, h->ev1);
+        (void)hipEventElapsedTime(&tms, h->evt0, h->evt1);
         status = map_device_error(c.error);
         if (status == MRRR_ENOMEM && attempt < 3) {
             scale *= 8.0;   // grow the node pool and retry
             continue;
         }
         *m = ph[0].m;
-        fill_stats(stats, c, ph[0].m, ms);
+        fill_stats(stats, c, ph[0].m, ms, tms);
         if (status == MRRR_OK && c.n_unverified > 0) status = MRRR_WARN_UNVERIFIED;
         break;
     }
