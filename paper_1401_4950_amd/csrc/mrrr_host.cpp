@@ -223,7 +223,7 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     ENS(ws.slist, sizeof(int32_t) * r);
     ENS(ws.arena, sizeof(double) * sz.arena);
     ENS(ws.ck, sizeof(double) * (size_t)std::max<int64_t>(sz.ck, 1));
-    ENS(ws.colbuf, sizeof(double) * r);
+    ENS(ws.colbuf, sizeof(double) * 2 * r);
     ENS(ws.perm, sizeof(int32_t) * 2 * r);
     ENS(ws.ctl, sizeof(Ctl));
 #undef ENS

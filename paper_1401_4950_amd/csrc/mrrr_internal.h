@@ -58,7 +58,7 @@ struct Problem {
     int64_t ck_base;  // checkpoint region (doubles) of this problem
     int64_t ck_slot0; // first slot with a checkpoint column
     int64_t ck_stride;
-    int32_t flags;    // device: bit0 = several blocks (final merge needed)
+    int32_t flags;    // device: bit0 several blocks; bit1 columns to permute
     int32_t pad;
 };
 
@@ -85,21 +85,31 @@ struct Node {
     double pad;
 };
 
+// Words that many workers hit (queue heads and tails, the pending count, the
+// error flag) each sit on a 256-byte line of their own, so that polling one
+// does not contend with updates of another.
+constexpr int kLineU64 = 32;
+
 struct Ctl {
-    uint64_t head[kNumQ];
-    uint64_t pad0[8 - kNumQ];
-    uint64_t tail[kNumQ];
-    uint64_t pad1[8 - kNumQ];
+    uint64_t head_[kNumQ * kLineU64];   // head of queue q at head_[q * kLineU64]
+    uint64_t tail_[kNumQ * kLineU64];
     int64_t pending;      // tasks pushed and not yet finished
+    int64_t pad_p[kLineU64 - 1];
     int32_t error;        // first error code raised on the device
     int32_t dmax;
+    int64_t pad_e[kLineU64 - 1];
     uint64_t arena_top;   // doubles handed out from the node arena
     int32_t node_top;
     int32_t pad2;
     int64_t slist_top;
+    int64_t pad_a[kLineU64 - 3];
     int64_t n_nodes, largest_cluster, n_unverified, n_fallback, n_nan;
     int64_t qd_steps, n_tasks, n_single, n_rqi, n_blocks;
     int64_t trace_top;
+#ifdef __HIPCC__
+    __device__ __host__ uint64_t* head(int q) { return head_ + q * kLineU64; }
+    __device__ __host__ uint64_t* tail(int q) { return tail_ + q * kLineU64; }
+#endif
 };
 
 struct TraceRec {       // mirrors mrrr_trace_t
@@ -135,8 +145,8 @@ struct Params {
     double* arena;
     uint64_t arena_cap;   // doubles
     double* ck;           // checkpoints of the twisted solver
-    double* colbuf;       // one column per problem (final merge)
-    int32_t* perm;        // per slot scratch for the final merge
+    double* colbuf;       // 2 doubles per slot: sort keys of the final merge
+    int32_t* perm;        // 2 per slot: column order of the final merge
     Ctl* ctl;
     int64_t total_rows;
     double gaptol, rtol, xi;

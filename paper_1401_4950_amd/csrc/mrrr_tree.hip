@@ -23,6 +23,8 @@
 //                  checkpoints, written straight into Z, normalised.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "mrrr_internal.h"
 
 namespace mrrr {
@@ -44,6 +46,42 @@ DEV int sbit(double x) { return (int)((unsigned long long)__double_as_longlong(x
 // and denominator are infinite, else num / den.
 DEV double qd_q(double num, double den) {
     return (__builtin_isinf(num) && __builtin_isinf(den)) ? 1.0 : num / den;
+}
+
+// Quotients from the hardware reciprocal (relative error below 2^-24 on
+// gfx950): with r ~ 1/b and e = 1 - b r, q1 = q0 (1 + e) for q0 = a r leaves
+// a relative error of order e^2, and the residual step q1 + (a - b q1) r
+// (Markstein's correction) brings it to the last bit.  A zero, infinite or
+// NaN operand, where the recurrences need IEEE semantics and the guard of
+// qd_q, always leaves a NaN here (0 * inf in e, inf - inf in the residual);
+// callers then recompute that quotient with qd_q.  One reciprocal serves all
+// quotients by the same pivot.
+struct Recip {
+    double b, r, e;
+};
+DEV Recip recip(double b) {
+    Recip o;
+    o.b = b;
+    o.r = __builtin_amdgcn_rcp(b);
+    o.e = __builtin_fma(-b, o.r, 1.0);
+    return o;
+}
+DEV double quot(const Recip& x, double a) {
+    const double q0 = a * x.r;
+    const double q1 = __builtin_fma(q0, x.e, q0);
+    const double rem = __builtin_fma(-x.b, q1, a);
+    return __builtin_fma(rem, x.r, q1);
+}
+// qd_q through the reciprocal: exact IEEE-and-guard fallback on NaN
+DEV double qd_qf(double num, const Recip& x) {
+    double q = quot(x, num);
+    if (__builtin_expect(__builtin_isnan(q), 0)) q = qd_q(num, x.b);
+    return q;
+}
+DEV double divf(double num, const Recip& x) {
+    double q = quot(x, num);
+    if (__builtin_expect(__builtin_isnan(q), 0)) q = num / x.b;
+    return q;
 }
 
 DEV uint64_t ld_acq64(uint64_t* p) {
@@ -110,8 +148,22 @@ DEV double unit_pm1(uint64_t seed, uint64_t idx) {
 
 // ---------------------------------------------------------------- LDS
 
+// A worker claims up to kPopMax consecutive tasks of a long queue at once.
+constexpr int kPopMax = 8;
+
+// One staged row of a representation or of T, read by all lanes:
+//   N-representation (D, L): d = d_i, dll = d_i l_i^2, dl = d_i l_i;
+//   T:                       d = alpha_i, dll = beta_{i-1}^2, dl = beta_{i-1}.
+// The two values the Sturm counts need come first (one 16-byte LDS read).
+struct alignas(32) QRow {
+    double d, dll, dl, pad;
+};
+typedef double dv2 __attribute__((ext_vector_type(2)));
+// (d, dll) of staged row k in one 16-byte LDS read
+#define QROW_DDLL(S, k) (*reinterpret_cast<const dv2*>(&(S).tr[(k)].d))
+
 struct Shared {
-    double ta[kTile], tb[kTile], tc[kTile];   // staged rows
+    QRow tr[kTile];                           // staged rows
     double m_lo[kWave], m_hi[kWave];          // multisection members
     double m_sig[kWave];
     int64_t m_slot[kWave];
@@ -119,7 +171,7 @@ struct Shared {
     int32_t m_flag[kWave];                    // bit0 lo verified, bit1 hi verified
     int32_t m_cnt[kWave];
     int32_t ulist[kWave];
-    Task task;
+    Task task[kPopMax];                       // tasks claimed by one pop
     int32_t ibc[8];
     double dbc[8];
     // what the finished task reports to the trace: depth, flags, child, x0, x1
@@ -151,14 +203,16 @@ DEV void rep_commit(Shared& S, const RepRow& f) {
     const int l = lane_id();
     const double dl = f.d * f.l;
     __syncthreads();
-    S.ta[l] = f.d;
-    S.tb[l] = dl;
-    S.tc[l] = dl * f.l;
+    QRow x;
+    x.d = f.d;
+    x.dll = dl * f.l;
+    x.dl = dl;
+    x.pad = 0.0;
+    S.tr[l] = x;
     __syncthreads();
 }
 
-// Rows of T: alpha_i in ta, beta_{i-1}^2 in tb, beta_{i-1} in tc (row i
-// couples to row i-1).
+// Rows of T (row i couples to row i-1).
 DEV RepRow T_fetch(const double* d, const double* e, int64_t base, int64_t n) {
     const int64_t r = base + lane_id();
     RepRow f;
@@ -174,15 +228,43 @@ DEV RepRow T_fetch(const double* d, const double* e, int64_t base, int64_t n) {
 DEV void T_commit(Shared& S, const RepRow& f) {
     const int l = lane_id();
     __syncthreads();
-    S.ta[l] = f.d;
-    S.tb[l] = f.l * f.l;
-    S.tc[l] = f.l;
+    QRow x;
+    x.d = f.d;
+    x.dll = f.l * f.l;
+    x.dl = f.l;
+    x.pad = 0.0;
+    S.tr[l] = x;
     __syncthreads();
 }
 
 // ------------------------------------------------------------ Sturm counts
 
 // NegCount(L D L^T, sigma) for one shift per lane (App. B, Alg. B.2).
+// Guarded: the quotient is 1 where both operands are infinite.
+DEV int negcount_rep_guarded(Shared& S, const double* D, const double* L, int64_t n, double sigma) {
+    double s = -sigma;
+    int cnt = 0;
+    RepRow f = rep_fetch(D, L, 0, n);
+    for (int64_t base = 0; base < n; base += kTile) {
+        rep_commit(S, f);
+        if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        for (int t = 0; t < lim; ++t) {
+            const dv2 x = QROW_DDLL(S, t);
+            const double dp = s + x.x;
+            cnt += sbit(dp);
+            s = qd_q(s, dp) * x.y - sigma;
+        }
+    }
+    return cnt;
+}
+
+// The same count with the reciprocal quotient and no guard.  The guard
+// matters only after a pivot was zero or infinite, and every such case
+// leaves a NaN that persists to the end of the pass (inf/inf, 0*inf and any
+// arithmetic on a NaN give NaN), so a final NaN sends the wave through the
+// guarded pass again.  Rows are read from LDS eight at a time, one group
+// ahead of the arithmetic, so that LDS latency stays off the recurrence.
 DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, double sigma) {
     double s = -sigma;
     int cnt = 0;
@@ -192,19 +274,36 @@ DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, dou
         if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         if (lim == kTile) {
-#pragma unroll 8
-            for (int t = 0; t < kTile; ++t) {
-                const double dp = s + S.ta[t];
-                cnt += sbit(dp);
-                s = qd_q(s, dp) * S.tc[t] - sigma;
+            dv2 cur[8], nxt[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) cur[u] = QROW_DDLL(S, u);
+#pragma unroll
+            for (int g = 0; g < kTile / 8; ++g) {
+                if (g + 1 < kTile / 8) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) nxt[u] = QROW_DDLL(S, (g + 1) * 8 + u);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double dp = s + cur[u].x;
+                    cnt += sbit(dp);
+                    s = quot(recip(dp), s) * cur[u].y - sigma;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
             }
         } else {
             for (int t = 0; t < lim; ++t) {
-                const double dp = s + S.ta[t];
+                const dv2 x = QROW_DDLL(S, t);
+                const double dp = s + x.x;
                 cnt += sbit(dp);
-                s = qd_q(s, dp) * S.tc[t] - sigma;
+                s = quot(recip(dp), s) * x.y - sigma;
             }
         }
+    }
+    if (wave_or(__builtin_isnan(s) ? 1 : 0)) {
+        const int c2 = negcount_rep_guarded(S, D, L, n, sigma);
+        if (__builtin_isnan(s)) cnt = c2;
     }
     return cnt;
 }
@@ -221,7 +320,8 @@ DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, doubl
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
-            piv = (i == 0) ? (S.ta[t] - sigma) : ((S.ta[t] - sigma) - S.tb[t] / piv);
+            const dv2 x = QROW_DDLL(S, t);
+            piv = (i == 0) ? (x.x - sigma) : ((x.x - sigma) - x.y / piv);
             cnt += sbit(piv);
         }
     }
@@ -439,13 +539,15 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
                 ck.at(i / kCkb, 0) = s;
                 ck.at(i / kCkb, 1) = h;
             }
-            const double dp = s + S.ta[t];
+            const QRow x = S.tr[t];
+            const double dp = s + x.d;
             cnt += sbit(dp);
-            const double q = qd_q(s, dp);
-            const double lp = S.tb[t] / dp;
+            const Recip rc = recip(dp);
+            const double q = qd_qf(s, rc);
+            const double lp = divf(x.dl, rc);
             h = 1.0 + (lp * lp) * h;
             dplast = dp;
-            s = q * S.tc[t] - lam;
+            s = q * x.dll - lam;
         }
     }
     steps += n;
@@ -471,25 +573,30 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
             if (c < cl && live) ck.at(c, 2) = p;      // p_{b1}
             // recompute s_i for the block from the forward checkpoint
             double sreg[kCkb];
+            QRow xr[kCkb];
+#pragma unroll
+            for (int t = 0; t < kCkb; ++t) {
+                const int k = (int)(b0 + t - tb);
+                xr[t] = S.tr[k < kTile ? k : kTile - 1];
+            }
             double sr = live ? ck.at(c, 0) : 0.0;
 #pragma unroll
             for (int t = 0; t < kCkb; ++t) {
                 sreg[t] = sr;
                 if (b0 + t < b1) {
-                    const int k = (int)(b0 + t - tb);
-                    const double dp = sr + S.ta[k];
-                    sr = qd_q(sr, dp) * S.tc[k] - lam;
+                    const double dp = sr + xr[t].d;
+                    sr = qd_qf(sr, recip(dp)) * xr[t].dll - lam;
                 }
             }
 #pragma unroll
             for (int t = kCkb - 1; t >= 0; --t) {
                 if (b0 + t < b1) {
-                    const int k = (int)(b0 + t - tb);
-                    const double om = p + S.tc[k];
-                    const double q = qd_q(p, om);
-                    const double um = S.tb[k] / om;
-                    const double gam = sreg[t] + S.ta[k] * q;
-                    p = q * S.ta[k] - lam;
+                    const double om = p + xr[t].dll;
+                    const Recip rc = recip(om);
+                    const double q = qd_qf(p, rc);
+                    const double um = divf(xr[t].dl, rc);
+                    const double gam = sreg[t] + xr[t].d * q;
+                    p = q * xr[t].d - lam;
                     g = 1.0 + (um * um) * g;
                     if (fabs(gam) <= best) {
                         best = fabs(gam);
@@ -549,15 +656,21 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
             const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
             if (b0 >= b1) continue;
             double ureg[kCkb];
+            QRow xr[kCkb];
+#pragma unroll
+            for (int t = 0; t < kCkb; ++t) {
+                const int k = (int)(b0 + t - tb);
+                xr[t] = S.tr[k < kTile ? k : kTile - 1];
+            }
             double pr = live ? ck.at(c, 2) : 0.0;
 #pragma unroll
             for (int t = kCkb - 1; t >= 0; --t) {
                 ureg[t] = 0.0;
                 if (b0 + t < b1) {
-                    const int k = (int)(b0 + t - tb);
-                    const double om = pr + S.tc[k];
-                    ureg[t] = (om != 0.0) ? S.tb[k] / om : __builtin_inf();
-                    pr = qd_q(pr, om) * S.ta[k] - lam;
+                    const double om = pr + xr[t].dll;
+                    const Recip rc = recip(om);
+                    ureg[t] = (om != 0.0) ? divf(xr[t].dl, rc) : __builtin_inf();
+                    pr = qd_qf(pr, rc) * xr[t].d - lam;
                 }
             }
 #pragma unroll
@@ -573,7 +686,7 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
                         zn = 0.0;
                         if (i - 1 >= r && i >= 1) {
                             const double dlm = D[i - 1] * L[i - 1];
-                            zn = -(dlm / S.tb[k]) * zm1;
+                            zn = -(dlm / S.tr[k].dl) * zm1;
                         }
                     }
                     if (i == r) zr1 = zn;
@@ -600,15 +713,21 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
             const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
             if (b0 >= b1) continue;
             double lreg[kCkb];
+            QRow xr[kCkb];
+#pragma unroll
+            for (int t = 0; t < kCkb; ++t) {
+                const int k = (int)(b0 + t - tb);
+                xr[t] = S.tr[k < kTile ? k : kTile - 1];
+            }
             double sr = live ? ck.at(c, 0) : 0.0;
 #pragma unroll
             for (int t = 0; t < kCkb; ++t) {
                 lreg[t] = 0.0;
                 if (b0 + t < b1) {
-                    const int k = (int)(b0 + t - tb);
-                    const double dp = sr + S.ta[k];
-                    lreg[t] = (dp != 0.0) ? S.tb[k] / dp : __builtin_inf();
-                    sr = qd_q(sr, dp) * S.tc[k] - lam;
+                    const double dp = sr + xr[t].d;
+                    const Recip rc = recip(dp);
+                    lreg[t] = (dp != 0.0) ? divf(xr[t].dl, rc) : __builtin_inf();
+                    sr = qd_qf(sr, rc) * xr[t].dll - lam;
                 }
             }
 #pragma unroll
@@ -624,7 +743,7 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
                         zn = 0.0;
                         if (i + 1 <= n - 2) {
                             const double dlp = D[i + 1] * L[i + 1];
-                            zn = -(dlp / S.tb[k]) * zp2;
+                            zn = -(dlp / S.tr[k].dl) * zp2;
                         }
                     }
                     zp2 = zc;
@@ -645,29 +764,53 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
 // cell carries a sequence number: pos when free for the producer of ticket
 // pos, pos + 1 when it holds that producer's task, pos + cap once consumed.
 
-DEV bool try_pop(const Params& P, int q, Task* out) {   // one lane
+// Claims tasks at the head of queue q into out[]; returns how many (0 when
+// nothing is published at the head).  One task at a time while the queue is
+// short, so that parallel work spreads over the workers; up to kPopMax
+// consecutive tasks when it holds more than twice the worker count, which
+// divides the traffic on the head counter.  Claimed cells that a pusher has
+// reserved but not yet filled are waited for (pushers fill reserved cells
+// without waiting on anything but the cell itself).
+DEV int try_pop(const Params& P, int q, Task* out) {   // one lane
     // Polling uses relaxed loads only: an acquire at agent scope invalidates
     // caches, and idle workers poll often.  The acquire fence follows a
     // successful claim.
     const uint64_t cap = P.qcap[q];
     for (int spin = 0; spin < 64; ++spin) {
-        uint64_t pos = __hip_atomic_load(&P.ctl->head[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t pos = __hip_atomic_load(P.ctl->head(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t cell = pos % cap;
         const uint64_t sq = __hip_atomic_load(&P.seq[q][cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (sq == pos + 1) {
-            if (__hip_atomic_compare_exchange_strong(&P.ctl->head[q], &pos, pos + 1, __ATOMIC_RELAXED,
+            const uint64_t tl = __hip_atomic_load(P.ctl->tail(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t k = 1;
+            if (tl > pos) {
+                const uint64_t share = (tl - pos) / (2 * (uint64_t)P.nworkers);
+                k = share < 1 ? 1 : (share > (uint64_t)kPopMax ? (uint64_t)kPopMax : share);
+            }
+            if (__hip_atomic_compare_exchange_strong(P.ctl->head(q), &pos, pos + k, __ATOMIC_RELAXED,
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 __atomic_thread_fence(__ATOMIC_ACQUIRE);
-                (void)ld_acq64(&P.seq[q][cell]);
-                *out = P.q[q][cell];
-                st_rel64(&P.seq[q][cell], pos + cap);
-                return true;
+                int got = 0;
+                for (uint64_t i = 0; i < k; ++i) {
+                    const uint64_t c = (pos + i) % cap;
+                    int wait = 0;
+                    while (ld_acq64(&P.seq[q][c]) != pos + i + 1) {
+                        if (++wait > (1 << 24)) {
+                            set_error(P, kErrInternal);
+                            return got;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    out[got++] = P.q[q][c];
+                    st_rel64(&P.seq[q][c], pos + i + cap);
+                }
+                return got;
             }
         } else if (sq < pos + 1) {
-            return false;   // nothing published at the head
+            return 0;   // nothing published at the head
         }
     }
-    return false;
+    return 0;
 }
 
 // Lane 0 reserves `count` tickets; every lane fills some of the cells.
@@ -679,7 +822,7 @@ DEV bool push_batch(const Params& P, int q, int count, Gen gen) {
     uint64_t first = 0;
     if (l == 0) {
         __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        first = __hip_atomic_fetch_add(&P.ctl->tail[q], (uint64_t)count, __ATOMIC_RELAXED,
+        first = __hip_atomic_fetch_add(P.ctl->tail(q), (uint64_t)count, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     }
     first = __shfl(first, 0);
@@ -714,10 +857,13 @@ DEV bool push_one(const Params& P, int q, Task t) {
 
 // Refinement slices of members [a, b] of a node (R-tasks of Sec. 4.1.3): the
 // slice size follows the thesis' rule of thumb -- about twice as many slices
-// as workers -- clamped to [slice_min, slice_max] eigenvalues.
-DEV void push_slices(const Params& P, int node_id, int a, int b, int mode) {
+// as workers -- clamped to [slice_min, slice_max] eigenvalues.  With many
+// matrices in one launch a block gets the share of the workers that its rows
+// are of all rows, so that small blocks are not cut into one-member slices.
+DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64_t block_rows) {
     const int64_t M = (int64_t)b - a + 1;
-    int64_t sz = (M + 2 * (int64_t)P.nworkers - 1) / (2 * (int64_t)P.nworkers);
+    const double share = (double)P.nworkers * (double)block_rows / (double)(P.total_rows > 0 ? P.total_rows : 1);
+    int64_t sz = (int64_t)ceil((double)M / (2.0 * fmax(share, 0.5)));
     if (sz < P.slice_min) sz = P.slice_min;
     if (sz > P.slice_max) sz = P.slice_max;
     const int ns = (int)((M + sz - 1) / sz);
@@ -782,18 +928,21 @@ DEV FacOut dstqds(Shared& S, const double* D, const double* L, int64_t n, double
         rep_commit(S, f);
         if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+#pragma unroll 4
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
-            const double dp = s + S.ta[t];
+            const QRow x = S.tr[t];
+            const double dp = s + x.d;
             if (act) Dp[i] = dp;
             ok &= (__builtin_isfinite(dp) && dp != 0.0) ? 1 : 0;
             gmax = fmax(gmax, fabs(dp));
-            if (i < n - 1) {
-                const double lp = S.tb[t] / dp;
-                if (act) Lp[i] = lp;
-                ok &= __builtin_isfinite(lp) ? 1 : 0;
-                s = qd_q(s, dp) * S.tc[t] - tau;
-            }
+            // the last row has dl = dll = 0 (rep_fetch): lp = 0 there, and
+            // Lp[n-1] lies inside the 2n-double block of the representation
+            const Recip rc = recip(dp);
+            const double lp = divf(x.dl, rc);
+            if (act) Lp[i] = lp;
+            ok &= __builtin_isfinite(lp) ? 1 : 0;
+            s = qd_qf(s, rc) * x.dll - tau;
         }
     }
     FacOut o;
@@ -816,13 +965,14 @@ DEV FacOut factor_T(Shared& S, const double* d, const double* e, int64_t n, doub
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
+            const QRow x = S.tr[t];
             double dv;
             if (i == 0) {
-                dv = S.ta[t] - mu;
+                dv = x.d - mu;
             } else {
-                const double lv = S.tc[t] / dprev;
+                const double lv = x.dl / dprev;
                 if (act) Ld[i - 1] = lv;
-                dv = (S.ta[t] - mu) - lv * S.tc[t];
+                dv = (x.d - mu) - lv * x.dl;
             }
             if (act) Dd[i] = dv;
             ok &= (__builtin_isfinite(dv) && (sgn > 0 ? dv > 0.0 : dv < 0.0)) ? 1 : 0;
@@ -1111,7 +1261,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         S.info_d[1] = spdiam;
     }
     add_stat(&P.ctl->n_nodes, 1);
-    push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull);
+    push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, blk.n);
 }
 
 DEV void load_members(Shared& S, const Params& P, int64_t sb, int a, int M) {
@@ -1341,7 +1491,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (l == 0) {
         __hip_atomic_fetch_max(&P.ctl->dmax, par.depth + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    push_slices(P, id, p, q, kModeClass);
+    push_slices(P, id, p, q, kModeClass, n);
 }
 
 // A bundle of singletons of one node, one per lane (Alg. 4.3): Rayleigh
@@ -1462,20 +1612,19 @@ using namespace mrrr;
 
 // The persistent worker: one wavefront per workgroup, looping over the task
 // queues until no task is pending (or an error / the watchdog stops it).
-extern "C" __global__ __launch_bounds__(64) void mrrr_tree_kernel(Params P) {
+extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void mrrr_tree_kernel(Params P) {
     __shared__ Shared S;
     const int l = lane_id();
     const uint64_t t0 = wall_clock64();
     int64_t steps = 0, ntask = 0, nsingle = 0;
     for (;;) {
         if (l == 0) {
-            int status = 0;
+            int status = 0, got = 0;
             int nap = 1;
             for (;;) {
                 if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { status = 2; break; }
-                bool got = false;
-                for (int qq = 0; qq < kNumQ && !got; ++qq) got = try_pop(P, qq, &S.task);
-                if (got) { status = 1; break; }
+                for (int qq = 0; qq < kNumQ && got == 0; ++qq) got = try_pop(P, qq, S.task);
+                if (got > 0) { status = 1; break; }
                 if (__hip_atomic_load(&P.ctl->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) { status = 2; break; }
                 if (wall_clock64() - t0 > P.timeout_ticks) {
                     int32_t expect = 0;
@@ -1489,50 +1638,58 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_tree_kernel(Params P) {
                 if (nap < 8) nap *= 2;
             }
             S.ibc[0] = status;
+            S.ibc[1] = got;
         }
         __syncthreads();
         const int status = S.ibc[0];
-        const Task tk = S.task;
+        const int ngot = S.ibc[1];
         __syncthreads();
-        if (status != 1) break;
-        __threadfence();
-        const uint64_t ts = wall_clock64();
-        if (l == 0) {
-            S.info_i[0] = 0; S.info_i[1] = 0; S.info_i[2] = -1; S.info_i[3] = 0;
-            S.info_d[0] = 0.0; S.info_d[1] = 0.0;
-        }
-        __syncthreads();
-        switch (tk.type) {
-            case kTaskRoot: task_root(S, P, tk.node, steps); break;
-            case kTaskRefine: task_refine(S, P, tk.node, tk.a, tk.b, steps); break;
-            case kTaskCluster: task_cluster(S, P, tk.node, tk.a, tk.b, steps); break;
-            case kTaskSingle: task_single(S, P, tk.node, tk.a, tk.b, steps); ++nsingle; break;
-            default: set_error(P, kErrInternal); break;
-        }
-        __threadfence();
-        __syncthreads();
-        if (P.trace && l == 0) {
-            const int64_t k = __hip_atomic_fetch_add(&P.ctl->trace_top, (int64_t)1, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-            if (k < P.trace_cap) {
-                TraceRec r;
-                r.type = tk.type;
-                r.worker = (int32_t)blockIdx.x;
-                r.node = tk.node;
-                r.depth = S.info_i[0];
-                r.a = tk.a;
-                r.b = tk.b;
-                r.t0 = (int64_t)ts;
-                r.t1 = (int64_t)wall_clock64();
-                r.x0 = S.info_d[0];
-                r.x1 = S.info_d[1];
-                r.flags = S.info_i[1];
-                r.child = S.info_i[2];
-                P.trace[k] = r;
+        // tasks claimed before an error still count as finished below
+        for (int bi = 0; bi < ngot; ++bi) {
+            const Task tk = S.task[bi];
+            __threadfence();
+            const uint64_t ts = wall_clock64();
+            if (l == 0) {
+                S.info_i[0] = 0; S.info_i[1] = 0; S.info_i[2] = -1; S.info_i[3] = 0;
+                S.info_d[0] = 0.0; S.info_d[1] = 0.0;
             }
+            __syncthreads();
+            if (status == 1) {
+                switch (tk.type) {
+                    case kTaskRoot: task_root(S, P, tk.node, steps); break;
+                    case kTaskRefine: task_refine(S, P, tk.node, tk.a, tk.b, steps); break;
+                    case kTaskCluster: task_cluster(S, P, tk.node, tk.a, tk.b, steps); break;
+                    case kTaskSingle: task_single(S, P, tk.node, tk.a, tk.b, steps); ++nsingle; break;
+                    default: set_error(P, kErrInternal); break;
+                }
+            }
+            __threadfence();
+            __syncthreads();
+            if (P.trace && l == 0 && status == 1) {
+                const int64_t k = __hip_atomic_fetch_add(&P.ctl->trace_top, (int64_t)1, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                if (k < P.trace_cap) {
+                    TraceRec r;
+                    r.type = tk.type;
+                    r.worker = (int32_t)blockIdx.x;
+                    r.node = tk.node;
+                    r.depth = S.info_i[0];
+                    r.a = tk.a;
+                    r.b = tk.b;
+                    r.t0 = (int64_t)ts;
+                    r.t1 = (int64_t)wall_clock64();
+                    r.x0 = S.info_d[0];
+                    r.x1 = S.info_d[1];
+                    r.flags = S.info_i[1];
+                    r.child = S.info_i[2];
+                    P.trace[k] = r;
+                }
+            }
+            ++ntask;
         }
-        if (l == 0) __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)-1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        ++ntask;
+        if (l == 0 && ngot > 0)
+            __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)-ngot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (status != 1) break;
     }
     add_stat(&P.ctl->qd_steps, steps);
     add_stat(&P.ctl->n_tasks, ntask);
@@ -1680,61 +1837,103 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
     }
 }
 
-// After the tree: eigenvalues of several blocks (or a rare out-of-order pair)
-// are put in ascending order, Z's columns permuted along (in place, one
-// column buffer per problem).
-extern "C" __global__ __launch_bounds__(64) void mrrr_finalize_kernel(Params P) {
-    const int l = lane_id();
-    const Problem pr = P.probs[blockIdx.x];
-    const int64_t m = pr.m;
+// After the tree: eigenvalues of several blocks, or values of one tight
+// cluster computed from different representations, may come out of
+// ascending order.  mrrr_sort_kernel (one workgroup per problem) leaves a
+// sorted problem alone; otherwise it sorts (w, column) pairs by a bitonic
+// network in scratch (keys at colbuf + 2 row0, columns at perm + 2 row0,
+// padded to a power of two <= 2 n), writes the sorted w, and marks the
+// problem (flags bit 1) for mrrr_permute_kernel, which moves Z's columns.
+extern "C" __global__ __launch_bounds__(1024) void mrrr_sort_kernel(Params P) {
+    __shared__ int unsorted;
+    Problem* prp = P.probs + blockIdx.x;
+    const int64_t m = prp->m;
+    const int tid = threadIdx.x, nt = blockDim.x;
     if (m < 2) return;
-    double* w = P.w + pr.woff;
-    int unsorted = 0;
-    for (int64_t i = l; i + 1 < m; i += kWave) unsorted |= (w[i] > w[i + 1]) ? 1 : 0;
-    if (!wave_or(unsorted)) return;
-    int32_t* rank = P.perm + pr.row0;
-    int32_t* src = P.perm + P.total_rows + pr.row0;
-    for (int64_t i = l; i < m; i += kWave) {
-        const double wi = w[i];
-        int64_t rk = 0;
-        for (int64_t k = 0; k < m; ++k) rk += (w[k] < wi || (w[k] == wi && k < i)) ? 1 : 0;
-        rank[i] = (int32_t)rk;
+    double* w = P.w + prp->woff;
+    if (tid == 0) unsorted = 0;
+    __syncthreads();
+    int u = 0;
+    for (int64_t i = tid; i + 1 < m; i += nt) u |= (w[i] > w[i + 1]) ? 1 : 0;
+    if (u) atomicOr(&unsorted, 1);
+    __syncthreads();
+    if (!unsorted) return;
+    int64_t p2 = 1;
+    while (p2 < m) p2 <<= 1;
+    double* key = P.colbuf + 2 * prp->row0;
+    int32_t* col = P.perm + 2 * prp->row0;
+    for (int64_t i = tid; i < p2; i += nt) {
+        key[i] = (i < m) ? w[i] : __builtin_inf();
+        col[i] = (i < m) ? (int32_t)i : INT32_MAX;
     }
-    __threadfence_block();
     __syncthreads();
-    for (int64_t i = l; i < m; i += kWave) src[rank[i]] = (int32_t)i;
-    __threadfence_block();
-    __syncthreads();
-    double* buf = P.colbuf + pr.row0;
-    for (int64_t i = l; i < m; i += kWave) buf[i] = w[src[i]];
-    __threadfence_block();
-    __syncthreads();
-    for (int64_t i = l; i < m; i += kWave) w[i] = buf[i];
-    __threadfence_block();
-    __syncthreads();
-    if (!P.jobz) return;
-    const int64_t n = pr.n, ldz = pr.ldz;
-    double* Z = P.Z + pr.zoff;
-    for (int64_t p0 = 0; p0 < m; ++p0) {
-        int32_t s0 = src[p0];
-        if (s0 < 0 || s0 == p0) continue;
-        for (int64_t i = l; i < n; i += kWave) buf[i] = Z[p0 * ldz + i];
-        int64_t pp = p0;
-        for (int64_t guard = 0; guard <= m; ++guard) {
-            const int32_t s = src[pp];
-            __syncthreads();
-            if (l == 0) src[pp] = -1;
-            __threadfence_block();
-            __syncthreads();
-            if (s == p0) {
-                for (int64_t i = l; i < n; i += kWave) Z[pp * ldz + i] = buf[i];
-                break;
+    for (int64_t k = 2; k <= p2; k <<= 1) {
+        for (int64_t j = k >> 1; j > 0; j >>= 1) {
+            for (int64_t i = tid; i < p2; i += nt) {
+                const int64_t x = i ^ j;
+                if (x <= i) continue;
+                const double ki = key[i], kx = key[x];
+                const int32_t ci = col[i], cx = col[x];
+                const bool gt = (ki > kx) || (ki == kx && ci > cx);   // (key, column) order
+                const bool up = (i & k) == 0;
+                if (up ? gt : !gt) {
+                    key[i] = kx; key[x] = ki;
+                    col[i] = cx; col[x] = ci;
+                }
             }
-            for (int64_t i = l; i < n; i += kWave) Z[pp * ldz + i] = Z[(int64_t)s * ldz + i];
-            pp = s;
+            __syncthreads();
         }
-        __threadfence_block();
-        __syncthreads();
+    }
+    for (int64_t i = tid; i < m; i += nt) w[i] = key[i];
+    if (tid == 0) prp->flags |= 2;
+}
+
+// Position i of a marked problem receives column col[i].  The permutation is
+// applied in place cycle by cycle: the wave that holds a cycle's smallest
+// index moves it, 512 rows at a time through registers.
+extern "C" __global__ __launch_bounds__(64) void mrrr_permute_kernel(Params P) {
+    constexpr int kR = 8;
+    const int l = lane_id();
+    const Problem pr = P.probs[blockIdx.y];
+    if (!(pr.flags & 2) || !P.jobz) return;
+    const int64_t m = pr.m, n = pr.n, ldz = pr.ldz;
+    const int32_t* col = P.perm + 2 * pr.row0;
+    double* Z = P.Z + pr.zoff;
+    for (int64_t p = blockIdx.x; p < m; p += gridDim.x) {
+        if (col[p] == p) continue;
+        bool leader = true;
+        int64_t q = col[p];
+        for (int64_t guard = 0; q != p; ++guard) {
+            if (q < p || guard > m) { leader = false; break; }
+            q = col[q];
+        }
+        if (!leader) continue;
+        for (int64_t r0 = 0; r0 < n; r0 += kWave * kR) {
+            double keep[kR];
+#pragma unroll
+            for (int u = 0; u < kR; ++u) {
+                const int64_t r = r0 + u * kWave + l;
+                keep[u] = (r < n) ? Z[p * ldz + r] : 0.0;
+            }
+            int64_t pp = p;
+            for (int64_t guard = 0; guard <= m; ++guard) {
+                const int64_t sidx = col[pp];
+                if (sidx == p) {
+#pragma unroll
+                    for (int u = 0; u < kR; ++u) {
+                        const int64_t r = r0 + u * kWave + l;
+                        if (r < n) Z[pp * ldz + r] = keep[u];
+                    }
+                    break;
+                }
+#pragma unroll
+                for (int u = 0; u < kR; ++u) {
+                    const int64_t r = r0 + u * kWave + l;
+                    if (r < n) Z[pp * ldz + r] = Z[sidx * ldz + r];
+                }
+                pp = sidx;
+            }
+        }
     }
 }
 
@@ -1795,7 +1994,9 @@ hipError_t launch_tree(const Params& P, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const Params& P, hipStream_t s) {
-    hipLaunchKernelGGL(mrrr_finalize_kernel, dim3(P.nprob), dim3(kWave), 0, s, P);
+    hipLaunchKernelGGL(mrrr_sort_kernel, dim3(P.nprob), dim3(1024), 0, s, P);
+    const unsigned gx = (unsigned)std::max(1, std::min(512, 65536 / std::max(1, (int)P.nprob)));
+    hipLaunchKernelGGL(mrrr_permute_kernel, dim3(gx, P.nprob), dim3(kWave), 0, s, P);
     return hipGetLastError();
 }
 
