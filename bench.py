@@ -11,7 +11,8 @@ resident in device memory before the timed region starts.
 
 Beside the headline the same run measures the two further forms:
   * batched: 4096 tridiagonals, sizes log-uniform in [32, 2048], in one
-    captured persistent launch, against 4096 plain per-matrix calls;
+    captured persistent launch with the autotuned per-bucket launch shape,
+    against 4096 plain per-matrix calls;
   * differentiation: forward + backward for 256 matrices of n = 512 (batched
     against per-matrix), one n = 8192 random matrix with an eigenvalue and
     eigenvector loss, and an eigenvalue-only loss on glued Wilkinson n = 8192.
@@ -119,19 +120,27 @@ def bench_batched(mr, torch, reps=5):
     dc = torch.tensor(d_cat, device=dev)
     ec = torch.tensor(e_cat, device=dev)
     pairs = int(off[-1])
-    # first call builds and captures the plan; the timed calls replay it
-    w, Z = mr.eigh_tridiagonal_batched(dc, ec, off)
-    del w, Z
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        w, Z = mr.eigh_tridiagonal_batched(dc, ec, off)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
+
+    def replay_median(tune):
+        # first call builds and captures the plan; the timed calls replay it
+        w, Z = mr.eigh_tridiagonal_batched(dc, ec, off, tune=tune)
         del w, Z
-    graph_s = float(np.median(times))
-    log(f"[bench] batched graph replay {graph_s * 1e3:.1f} ms")
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            w, Z = mr.eigh_tridiagonal_batched(dc, ec, off, tune=tune)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            del w, Z
+        return float(np.median(times))
+
+    default_s = replay_median(None)
+    log(f"[bench] batched graph replay, default launch shape {default_s * 1e3:.1f} ms")
+    from paper_1401_4950_amd import autotune
+    table, rep = autotune.tune_batched(dc, ec, off, log=log)
+    graph_s = replay_median(table)
+    log(f"[bench] batched graph replay, tuned {graph_s * 1e3:.1f} ms (tuning took {rep.seconds:.1f} s)")
     # plain: one call per matrix on the same stream
     views = [(dc[int(off[b]):int(off[b + 1])], ec[int(off[b]):int(off[b + 1]) - 1]) for b in range(len(sizes))]
     for d, e in views[:16]:
@@ -148,9 +157,13 @@ def bench_batched(mr, torch, reps=5):
         "eigenpairs": pairs,
         "sum_n2": int(np.sum(np.asarray(sizes, dtype=np.int64) ** 2)),
         "graph_ms": graph_s * 1e3,
+        "graph_ms_default_shape": default_s * 1e3,
         "plain_ms": plain_s * 1e3,
         "eigenpairs_per_s": pairs / graph_s,
         "speedup_vs_plain": plain_s / graph_s,
+        "autotune": {"seconds": rep.seconds, "sample_ms": rep.sample_ms,
+                     "default_sample_ms": rep.default_sample_ms, "tried": rep.tried,
+                     "buckets": {f"2^{k}": v["config"] for k, v in sorted(rep.buckets.items())}},
     }
 
 

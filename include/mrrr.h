@@ -77,6 +77,14 @@ typedef struct {
     double arena_scale;      /* node-pool size factor (1.0); grows on ENOMEM */
     void *trace;             /* device, optional: trace_cap mrrr_trace_t records */
     int64_t trace_cap;       /* 0 = no trace */
+    int32_t lanes_per_eig;   /* most lanes one refinement gives one eigenvalue
+                                (multisection points, a power of two 1..64);
+                                64 by default */
+    int32_t bundle;          /* singletons per task (1..64), 64 by default */
+    const int32_t *tune;     /* host, optional, batched calls only: for matrix
+                                b, tune[3b..3b+2] = lanes_per_eig, bundle,
+                                slice_max (an entry <= 0 keeps the value
+                                above); read during the call only */
 } mrrr_options_t;
 
 /* One record per executed device task (the per-task timeline of the

@@ -16,6 +16,8 @@ from __future__ import annotations
 import ctypes
 import threading
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -115,13 +117,16 @@ def eigh_tridiagonal(d, e, select="a", select_range=None, eigvals_only=False, op
 
 
 def eigh_tridiagonal_batched(d_cat, e_cat, n_offsets, z_offsets=None, eigvals_only=False,
-                             options=None, out=None):
+                             options=None, out=None, tune=None):
     """All eigenpairs of many tridiagonals in one persistent launch.
 
     n_offsets: host sequence of batch+1 row offsets; matrix b occupies rows
     [n_offsets[b], n_offsets[b+1]) of d_cat and e_cat (e_cat keeps one
     padding slot per matrix).  Returns (w_cat, Z_cat) with matrix b's n_b x
     n_b eigenvectors column-major at z_offsets[b] (packed by default).
+    tune: optional (batch, 3) integer table of per-matrix launch shapes
+    (lanes per eigenvalue, singleton bundle, slice cap), e.g. from
+    ``autotune.tune_batched``.
     """
     d_cat = _dev_f64(d_cat, "d_cat")
     e_cat = _dev_f64(e_cat, "e_cat")
@@ -133,6 +138,12 @@ def eigh_tridiagonal_batched(d_cat, e_cat, n_offsets, z_offsets=None, eigvals_on
     if z_offsets is not None:
         zarr = (ctypes.c_int64 * batch)(*[int(x) for x in z_offsets])
     o = _options(options, not eigvals_only)
+    tune_arr = None
+    if tune is not None:
+        tune_arr = np.ascontiguousarray(np.asarray(tune, dtype=np.int32).reshape(-1))
+        if tune_arr.size != 3 * batch:
+            raise ValueError(f"tune must hold 3 entries per matrix ({3 * batch}), got {tune_arr.size}")
+        o.tune = tune_arr.ctypes.data
     if out is not None:
         w_cat, Z_cat = out
     else:

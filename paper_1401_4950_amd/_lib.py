@@ -32,6 +32,8 @@ class Options(ctypes.Structure):
         ("slice_min", ctypes.c_int32), ("slice_max", ctypes.c_int32),
         ("timeout_s", ctypes.c_double), ("arena_scale", ctypes.c_double),
         ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int64),
+        ("lanes_per_eig", ctypes.c_int32), ("bundle", ctypes.c_int32),
+        ("tune", ctypes.c_void_p),
     ]
 
 

@@ -73,6 +73,7 @@ struct Sizes {
 struct mrrr_batched_plan_s {
     int64_t batch = 0;
     std::vector<int64_t> noff, zoff;
+    std::vector<int32_t> tune;   // copy of the per-matrix table (empty: none)
     mrrr_options_t opts{};
     const double *d = nullptr, *e = nullptr;
     double *w = nullptr, *Z = nullptr;
@@ -118,6 +119,9 @@ extern "C" void mrrr_default_options(mrrr_options_t* o) {
     o->workers = 0;
     o->slice_min = 2;
     o->slice_max = 64;
+    o->lanes_per_eig = 64;
+    o->bundle = 64;
+    o->tune = nullptr;
     o->timeout_s = 30.0;
     o->arena_scale = 1.0;
 }
@@ -264,7 +268,6 @@ void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int worker
     P.max_tries = o.max_shift_tries;
     P.max_depth = o.max_depth;
     P.slice_min = std::max(1, o.slice_min);
-    P.slice_max = std::min(kWave, std::max(P.slice_min, o.slice_max));
     P.sign_conv = o.sign_convention;
     P.nworkers = workers;
     P.timeout_ticks = (uint64_t)std::max(1.0, o.timeout_s * wall_khz * 1000.0);
@@ -279,7 +282,27 @@ int check_options(const mrrr_options_t& o) {
     if (o.max_rqi < 0 || o.max_shift_tries < 1 || o.max_depth < 1) return 1;
     if (!(o.timeout_s > 0.0)) return 1;
     if (o.trace_cap < 0) return 1;
+    if (o.lanes_per_eig < 1 || o.lanes_per_eig > kWave || (o.lanes_per_eig & (o.lanes_per_eig - 1))) return 1;
+    if (o.bundle < 1 || o.bundle > kWave) return 1;
     return 0;
+}
+
+// Launch shape of one matrix: the scalar options, or entry b of the
+// per-matrix table where it is positive (lanes rounded down to a power of
+// two, everything clamped to what the kernel supports).
+void apply_tune(Problem& pr, const mrrr_options_t& o, const int32_t* tune, int64_t b) {
+    int lanes = o.lanes_per_eig, bundle = o.bundle, smax = o.slice_max;
+    if (tune) {
+        if (tune[3 * b] > 0) lanes = tune[3 * b];
+        if (tune[3 * b + 1] > 0) bundle = tune[3 * b + 1];
+        if (tune[3 * b + 2] > 0) smax = tune[3 * b + 2];
+    }
+    lanes = std::min(kWave, std::max(1, lanes));
+    int p2 = 1;
+    while (p2 * 2 <= lanes) p2 *= 2;
+    pr.lanes = (int16_t)p2;
+    pr.bundle = (int16_t)std::min(kWave, std::max(1, bundle));
+    pr.slice_max = std::min(kWave, std::max(std::max(1, o.slice_min), smax));
 }
 
 Sizes base_sizes(int64_t rows, int64_t nprob, int64_t kwork, int64_t nmax, double arena_scale) {
@@ -385,6 +408,7 @@ extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const do
     pr.vl = vl;
     pr.vu = vu;
     pr.range = range;
+    apply_tune(pr, o, nullptr, 0);
     int64_t kwork = n;
     pr.ck_base = 0;
     pr.ck_slot0 = 0;
@@ -455,6 +479,7 @@ int build_plan(mrrr_handle_t h, mrrr_batched_plan_s* pl) {
         pr.il = 1;
         pr.iu = nb;
         pr.range = MRRR_RANGE_ALL;
+        apply_tune(pr, pl->opts, pl->tune.empty() ? nullptr : pl->tune.data(), b);
         pr.ck_base = ck;
         pr.ck_slot0 = pl->noff[b];
         pr.ck_stride = nb;
@@ -503,7 +528,12 @@ int build_plan(mrrr_handle_t h, mrrr_batched_plan_s* pl) {
 bool same_plan(const mrrr_batched_plan_s* pl, int64_t batch, const int64_t* noff, const int64_t* zoff,
                const mrrr_options_t& o, const double* d, const double* e, double* w, double* Z) {
     if (!pl || pl->batch != batch) return false;
-    if (std::memcmp(&pl->opts, &o, sizeof(o)) != 0) return false;
+    mrrr_options_t a = pl->opts, b = o;
+    a.tune = nullptr;   // the table is compared by content below
+    b.tune = nullptr;
+    if (std::memcmp(&a, &b, sizeof(a)) != 0) return false;
+    if ((o.tune == nullptr) != pl->tune.empty()) return false;
+    if (o.tune && std::memcmp(pl->tune.data(), o.tune, sizeof(int32_t) * 3 * (size_t)batch) != 0) return false;
     if (pl->d != d || pl->e != e || pl->w != w || pl->Z != Z) return false;
     if (std::memcmp(pl->noff.data(), noff, sizeof(int64_t) * (size_t)(batch + 1)) != 0) return false;
     if ((zoff == nullptr) != pl->zoff.empty()) return false;
@@ -547,7 +577,9 @@ extern "C" int mrrr_dstemr_batched(mrrr_handle_t h, int64_t batch, const int64_t
             pl->batch = batch;
             pl->noff.assign(n_offsets, n_offsets + batch + 1);
             if (z_offsets) pl->zoff.assign(z_offsets, z_offsets + batch);
+            if (oo.tune) pl->tune.assign(oo.tune, oo.tune + 3 * batch);
             pl->opts = oo;
+            pl->opts.tune = nullptr;   // never kept: the caller owns the table
             pl->d = d_cat;
             pl->e = e_cat;
             pl->w = w_cat;

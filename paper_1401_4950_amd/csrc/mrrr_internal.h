@@ -59,6 +59,9 @@ struct Problem {
     int64_t ck_slot0; // first slot with a checkpoint column
     int64_t ck_stride;
     int32_t flags;    // device: bit0 several blocks; bit1 columns to permute
+    int16_t lanes;    // most multisection lanes per eigenvalue (power of two)
+    int16_t bundle;   // singletons per S-task
+    int32_t slice_max;  // largest refinement slice
     int32_t pad;
 };
 
@@ -151,7 +154,7 @@ struct Params {
     int64_t total_rows;
     double gaptol, rtol, xi;
     uint64_t seed;
-    int32_t max_rqi, max_tries, max_depth, slice_min, slice_max, sign_conv;
+    int32_t max_rqi, max_tries, max_depth, slice_min, sign_conv, pad_o;
     uint64_t timeout_ticks;
     TraceRec* trace;
     int64_t trace_cap;

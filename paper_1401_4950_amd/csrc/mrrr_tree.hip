@@ -83,6 +83,17 @@ DEV double divf(double num, const Recip& x) {
     if (__builtin_expect(__builtin_isnan(q), 0)) q = num / x.b;
     return q;
 }
+// Whole-pass forms: G = false takes the reciprocal quotient with no per-row
+// test (the caller checks for a NaN once the pass is over and then runs the
+// pass again with G = true, the IEEE quotient and the guard).
+template <bool G>
+DEV double qq(double num, const Recip& x) {
+    return G ? qd_q(num, x.b) : quot(x, num);
+}
+template <bool G>
+DEV double dq(double num, const Recip& x) {
+    return G ? num / x.b : quot(x, num);
+}
 
 DEV uint64_t ld_acq64(uint64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -343,6 +354,7 @@ struct MemberCtx {
     int32_t na, nb;      // member range of the node (neighbour tests)
     int64_t slot_base;   // slot = slot_base + j
     bool publish;        // write brackets to global memory after every pass
+    int lanes;           // most lanes per unconverged member (power of two)
 };
 
 DEV double dist0(double a, double b) {   // distance of [a, b] from zero
@@ -432,7 +444,7 @@ DEV void refine_members(Shared& S, const Params& P, const double* D, const doubl
         if (need != 0) S.ulist[__popcll(um & ((1ull << l) - 1ull))] = l;
         __syncthreads();
         int Lg = 1;
-        while (Lg * 2 * nu <= kWave) Lg *= 2;
+        while (Lg * 2 * nu <= kWave && Lg * 2 <= C.lanes) Lg *= 2;
         const int u = l / Lg;
         const int t = l % Lg;
         const bool valid = (u < nu);
@@ -520,10 +532,13 @@ struct TwistOut {
     int r;         // twist index (0-based row)
     double gam;    // gamma_r
     double nrm2;   // ||z||^2 with z_r = 1
+    int bad;       // reciprocal pass met a special operand (redo guarded)
+    int guarded;   // the result (and the lane's checkpoints) came from the IEEE pass
 };
 
-DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
-                     const CkPtr& ck, int64_t& steps) {
+template <bool G>
+DEV TwistOut twisted_impl(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
+                          const CkPtr& ck, int64_t& steps) {
     TwistOut o;
     // ---- forward: dstqds with checkpoints of (s, h)
     double s = -lam, h = 1.0, dplast = 0.0;
@@ -543,8 +558,8 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
             const double dp = s + x.d;
             cnt += sbit(dp);
             const Recip rc = recip(dp);
-            const double q = qd_qf(s, rc);
-            const double lp = divf(x.dl, rc);
+            const double q = qq<G>(s, rc);
+            const double lp = dq<G>(x.dl, rc);
             h = 1.0 + (lp * lp) * h;
             dplast = dp;
             s = q * x.dll - lam;
@@ -585,7 +600,7 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
                 sreg[t] = sr;
                 if (b0 + t < b1) {
                     const double dp = sr + xr[t].d;
-                    sr = qd_qf(sr, recip(dp)) * xr[t].dll - lam;
+                    sr = qq<G>(sr, recip(dp)) * xr[t].dll - lam;
                 }
             }
 #pragma unroll
@@ -593,8 +608,8 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
                 if (b0 + t < b1) {
                     const double om = p + xr[t].dll;
                     const Recip rc = recip(om);
-                    const double q = qd_qf(p, rc);
-                    const double um = divf(xr[t].dl, rc);
+                    const double q = qq<G>(p, rc);
+                    const double um = dq<G>(xr[t].dl, rc);
                     const double gam = sreg[t] + xr[t].d * q;
                     p = q * xr[t].d - lam;
                     g = 1.0 + (um * um) * g;
@@ -629,8 +644,32 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
     o.r = r;
     o.gam = gam_r;
     o.nrm2 = hr + g_r - 1.0;
+    // a zero or infinite pivot anywhere leaves a NaN in the last s or p
+    o.bad = (__builtin_isnan(s) || __builtin_isnan(p)) ? 1 : 0;
     return o;
 }
+
+// The twisted factorisation with reciprocal quotients; the lanes that met a
+// zero or infinite pivot repeat it with IEEE quotients and the guard.  Only
+// those lanes are redone: a lane's eigenvector must later be solved with the
+// same arithmetic that produced its checkpoints, because near a tiny pivot
+// the rounding of one quotient cancels only against that of its neighbours
+// in the same computation.
+DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
+                     const CkPtr& ck, int64_t& steps) {
+    TwistOut o = twisted_impl<false>(S, D, L, n, lam, live, ck, steps);
+    o.guarded = 0;
+    const bool redo = live && o.bad;
+    if (wave_or(redo ? 1 : 0)) {
+        const TwistOut g = twisted_impl<true>(S, D, L, n, lam, redo, ck, steps);
+        if (redo) {
+            o = g;
+            o.guarded = 1;
+        }
+    }
+    return o;
+}
+
 
 // Solve N_r^T z = e_r (Alg. 3.7): z_r = 1; z_{i+1} = -uminus_i z_i above r;
 // z_i = -lplus_i z_{i+1} below r; the zero-pivot rules of Alg. 3.7 where a
@@ -638,9 +677,10 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
 // recomputed per 16-row block from the checkpoints of the accepted
 // factorisation.  Each value is scaled by `scale` and stored to zcol[row]
 // when `write`; sum of squares returned.
-DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, double lam,
-                        bool live, int r, double scale, const CkPtr& ck, double* zcol, bool write,
-                        int64_t& steps) {
+template <bool G>
+DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_t n, double lam,
+                             bool live, int r, double scale, const CkPtr& ck, double* zcol, bool write,
+                             int64_t& steps) {
     double ss = live ? 1.0 : 0.0;
     if (live && write) zcol[r] = scale;
     // ---- upward: rows r+1 .. n-1
@@ -669,8 +709,8 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
                 if (b0 + t < b1) {
                     const double om = pr + xr[t].dll;
                     const Recip rc = recip(om);
-                    ureg[t] = (om != 0.0) ? divf(xr[t].dl, rc) : __builtin_inf();
-                    pr = qd_qf(pr, rc) * xr[t].d - lam;
+                    ureg[t] = (!G || om != 0.0) ? dq<G>(xr[t].dl, rc) : __builtin_inf();
+                    pr = qq<G>(pr, rc) * xr[t].d - lam;
                 }
             }
 #pragma unroll
@@ -726,8 +766,8 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
                 if (b0 + t < b1) {
                     const double dp = sr + xr[t].d;
                     const Recip rc = recip(dp);
-                    lreg[t] = (dp != 0.0) ? divf(xr[t].dl, rc) : __builtin_inf();
-                    sr = qd_qf(sr, rc) * xr[t].dll - lam;
+                    lreg[t] = (!G || dp != 0.0) ? dq<G>(xr[t].dl, rc) : __builtin_inf();
+                    sr = qq<G>(sr, rc) * xr[t].dll - lam;
                 }
             }
 #pragma unroll
@@ -755,6 +795,22 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
         }
     }
     steps += 2 * n;
+    return ss;
+}
+
+// Getvec in the arithmetic of the lane's accepted factorisation: reciprocal
+// quotients, or IEEE quotients with the guard for lanes whose factorisation
+// needed them (`guarded`); a NaN from the reciprocal pass (the zero-pivot
+// rules of Alg. 3.7 need IEEE infinities) also sends a lane to the IEEE
+// pass, which rewrites every entry of its column.
+DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live, int r,
+                        double scale, const CkPtr& ck, double* zcol, bool write, bool guarded, int64_t& steps) {
+    double ss = solve_vector_impl<false>(S, D, L, n, lam, live && !guarded, r, scale, ck, zcol, write, steps);
+    const bool redo = live && (guarded || __builtin_isnan(ss));
+    if (wave_or(redo ? 1 : 0)) {
+        const double sg = solve_vector_impl<true>(S, D, L, n, lam, redo, r, scale, ck, zcol, write, steps);
+        if (redo) ss = sg;
+    }
     return ss;
 }
 
@@ -860,12 +916,12 @@ DEV bool push_one(const Params& P, int q, Task t) {
 // as workers -- clamped to [slice_min, slice_max] eigenvalues.  With many
 // matrices in one launch a block gets the share of the workers that its rows
 // are of all rows, so that small blocks are not cut into one-member slices.
-DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64_t block_rows) {
+DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64_t block_rows, int smax) {
     const int64_t M = (int64_t)b - a + 1;
     const double share = (double)P.nworkers * (double)block_rows / (double)(P.total_rows > 0 ? P.total_rows : 1);
     int64_t sz = (int64_t)ceil((double)M / (2.0 * fmax(share, 0.5)));
+    if (sz > smax) sz = smax;
     if (sz < P.slice_min) sz = P.slice_min;
-    if (sz > P.slice_max) sz = P.slice_max;
     const int ns = (int)((M + sz - 1) / sz);
     if (lane_id() == 0)
         __hip_atomic_store(&P.nodes[node_id].pending, ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1114,15 +1170,16 @@ DEV void classify(Shared& S, const Params& P, int node_id) {
             }
         }
     }
-    // singleton bundles of up to 64
-    const int nb = (nsing + kWave - 1) / kWave;
+    // singleton bundles of the matrix's bundle size (at most one per lane)
+    const int bs = P.probs[blk.prob].bundle;
+    const int nb = (nsing + bs - 1) / bs;
     push_batch(P, kQSingle, nb, [&](int k) {
         Task t;
         t.type = kTaskSingle;
         t.node = node_id;
-        t.a = (int)(off + (int64_t)k * kWave);
-        const int rem = nsing - k * kWave;
-        t.b = rem < kWave ? rem : kWave;
+        t.a = (int)(off + (int64_t)k * bs);
+        const int rem = nsing - k * bs;
+        t.b = rem < bs ? rem : bs;
         return t;
     });
     stat_max(&P.ctl->largest_cluster, largest);
@@ -1261,7 +1318,8 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         S.info_d[1] = spdiam;
     }
     add_stat(&P.ctl->n_nodes, 1);
-    push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, blk.n);
+    push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, blk.n,
+                P.probs[blk.prob].slice_max);
 }
 
 DEV void load_members(Shared& S, const Params& P, int64_t sb, int a, int M) {
@@ -1296,6 +1354,7 @@ DEV void task_refine(Shared& S, const Params& P, int node_id, int a, int braw, i
     C.nb = nd.b;
     C.slot_base = sb;
     C.publish = true;
+    C.lanes = P.probs[blk.prob].lanes;
     refine_members(S, P, D, L, n, M, C, steps);
     if (l < M) P.vflag[S.m_slot[l]] = (uint8_t)(S.m_flag[l] & 3);
     if (mode == kModeFull && !P.jobz && l < M) {
@@ -1347,6 +1406,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     C.nb = -1;
     C.slot_base = sb;
     C.publish = true;
+    C.lanes = P.probs[blk.prob].lanes;
 #ifdef MRRR_DEBUG_TRACE
     const double dbg_lo_in = ld_rlx_d(P.lo + sb + p), dbg_hi_in = ld_rlx_d(P.hi + sb + p);
 #endif
@@ -1491,7 +1551,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (l == 0) {
         __hip_atomic_fetch_max(&P.ctl->dmax, par.depth + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    push_slices(P, id, p, q, kModeClass, n);
+    push_slices(P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max);
 }
 
 // A bundle of singletons of one node, one per lane (Alg. 4.3): Rayleigh
@@ -1518,39 +1578,25 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
     ck.base = P.ck + pr.ck_base + (slot - pr.ck_slot0);
     ck.stride = pr.ck_stride;
     const double tol1 = (double)n * kEps, tol2 = 2.0 * kEps;
-    bool done = !act, force = false;
+    // Alg. 4.3: Rayleigh-quotient steps while the correction improves the
+    // eigenvalue -- right sign, inside the bracket, and at most half the
+    // previous correction (a correction that stops shrinking is at the
+    // rounding floor of the representation); otherwise bisection to full
+    // accuracy.  Lanes that need bisection wait, so that one refinement
+    // round serves all of them; one more factorisation at the refined value
+    // is then accepted.
+    bool done = !act, need_fb = false, force = false, tg = false;
+    double prev = __builtin_inf();
     int r = 0;
     double nrm2 = 1.0;
     int64_t nrqi = 0, nfb = 0;
     for (int it = 0; it < P.max_rqi + 4; ++it) {
-        if (__ballot(!done) == 0ull) break;
-        const bool live = !done;
-        const TwistOut tw = twisted(S, D, L, n, lam, live, ck, steps);
-        nrqi += __popcll(__ballot(live));
-        bool fb = false;
-        if (live) {
-            const bool below = tw.neg >= j;       // lambda_j < lam
-            if (below) { hi = fmin(hi, lam); vf |= 2; }
-            else { lo = fmax(lo, lam); vf |= 1; }
-            const bool fin = __builtin_isfinite(tw.nrm2) && tw.nrm2 > 0.0;
-            const double resid = fin ? fabs(tw.gam) / sqrt(tw.nrm2) : __builtin_inf();
-            const double rqc = fin ? tw.gam / tw.nrm2 : 0.0;
-            if (force || (fin && (resid <= tol1 * gap || fabs(rqc) <= tol2 * fabs(lam)))) {
-                done = true;
-                r = tw.r;
-                nrm2 = tw.nrm2;
-            } else {
-                const bool sign_ok = below ? (rqc <= 0.0) : (rqc >= 0.0);
-                const double cand = lam + rqc;
-                if (fin && sign_ok && cand >= lo && cand <= hi && it < P.max_rqi) lam = cand;
-                else fb = true;
-            }
-        }
-        // bisection fallback to full accuracy for the lanes that need it
-        const uint64_t fm = __ballot(fb);
-        if (fm) {
+        const bool live = !done && !need_fb;
+        if (__ballot(live) == 0ull) {
+            const uint64_t fm = __ballot(need_fb);
+            if (fm == 0ull) break;
             const int k = __popcll(fm & ((1ull << l) - 1ull));
-            if (fb) {
+            if (need_fb) {
                 S.m_j[k] = j;
                 S.m_slot[k] = slot;
                 S.m_lo[k] = lo;
@@ -1564,16 +1610,44 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
             C.nb = -1;
             C.slot_base = sb;
             C.publish = false;
+            C.lanes = kWave;
             refine_members(S, P, D, L, n, __popcll(fm), C, steps);
-            if (fb) {
+            if (need_fb) {
                 lo = S.m_lo[k];
                 hi = S.m_hi[k];
                 vf = S.m_flag[k];
                 lam = lo + 0.5 * (hi - lo);
                 force = true;
+                need_fb = false;
             }
             nfb += __popcll(fm);
             __syncthreads();
+            continue;
+        }
+        const TwistOut tw = twisted(S, D, L, n, lam, live, ck, steps);
+        nrqi += __popcll(__ballot(live));
+        if (live) {
+            const bool below = tw.neg >= j;       // lambda_j < lam
+            if (below) { hi = fmin(hi, lam); vf |= 2; }
+            else { lo = fmax(lo, lam); vf |= 1; }
+            const bool fin = __builtin_isfinite(tw.nrm2) && tw.nrm2 > 0.0;
+            const double resid = fin ? fabs(tw.gam) / sqrt(tw.nrm2) : __builtin_inf();
+            const double rqc = fin ? tw.gam / tw.nrm2 : 0.0;
+            if (force || (fin && (resid <= tol1 * gap || fabs(rqc) <= tol2 * fabs(lam)))) {
+                done = true;
+                r = tw.r;
+                nrm2 = tw.nrm2;
+                tg = tw.guarded != 0;
+            } else {
+                const bool sign_ok = below ? (rqc <= 0.0) : (rqc >= 0.0);
+                const double cand = lam + rqc;
+                if (fin && sign_ok && cand >= lo && cand <= hi && fabs(rqc) <= 0.5 * prev && it < P.max_rqi) {
+                    lam = cand;
+                    prev = fabs(rqc);
+                } else {
+                    need_fb = true;
+                }
+            }
         }
     }
     if (__ballot(act && !done) != 0ull) {
@@ -1586,11 +1660,11 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
         const bool fin = __builtin_isfinite(nrm2) && nrm2 > 0.0;
         if (__ballot(act && !fin) != 0ull) {
             // a zero pivot spoiled the nested norm: sum the squares directly
-            const double ss = solve_vector(S, D, L, n, lam, act, r, 1.0, ck, zcol, false, steps);
+            const double ss = solve_vector(S, D, L, n, lam, act, r, 1.0, ck, zcol, false, tg, steps);
             if (!fin) nrm2 = ss;
         }
         const double scale = 1.0 / sqrt(nrm2);
-        solve_vector(S, D, L, n, lam, act, r, scale, ck, zcol, true, steps);
+        solve_vector(S, D, L, n, lam, act, r, scale, ck, zcol, true, tg, steps);
         if (act && (pr.flags & 1)) {
             // several blocks: the rest of the column is zero
             double* zc = P.Z + pr.zoff + col * pr.ldz;

@@ -192,3 +192,38 @@ def test_backward_batched_vs_single():
         if nb > 1:
             assert torch.allclose(e1, eb[r0:r0 + nb - 1], rtol=1e-12, atol=1e-12)
         zo += nb * nb
+
+
+def test_launch_shapes_plain(orc):
+    """Unusual launch shapes (one lane per eigenvalue, small bundles and
+    slices) give the same parity on the plain solve."""
+    for fam, n in (("random", 700), ("glued_wilkinson", 420), ("121", 500)):
+        d, e = ti.family(fam, n, 0)
+        for lanes, bundle, smax in ((1, 8, 2), (2, 64, 16), (64, 1, 64)):
+            from _gpu_util import gpu_solve
+            w, Z = gpu_solve(d, e, lanes_per_eig=lanes, bundle=bundle, slice_max=smax)
+            wo, Zo = orc.solve(d, e)
+            check_pairs(d, e, w, Z, wo, Zo)
+
+
+def test_batched_tuned_table(orc):
+    """A tuned per-matrix table (from the autotuner on the device) and a
+    hand-made mixed table both give oracle parity."""
+    import torch
+    import paper_1401_4950_amd as mr
+    from paper_1401_4950_amd import autotune
+    sizes, off, d_cat, e_cat = ti.batch_uniform(48, seed=9)
+    grid = {"lanes_per_eig": (1, 64), "bundle": (16, 64), "slice_max": (64,)}
+    table, rep = autotune.tune_batched(d_cat, e_cat, off, grid=grid, reps=1, rows_per_sample=6000)
+    assert table.shape == (48, 3) and rep.buckets
+    rng = np.random.default_rng(4)
+    mixed = np.stack([rng.choice([1, 2, 8, 64], 48), rng.choice([1, 7, 32, 64], 48),
+                      rng.choice([2, 5, 64], 48)], axis=1).astype(np.int32)
+    for tab in (table, mixed):
+        w_cat, Z_cat = mr.eigh_tridiagonal_batched(to_dev(d_cat), to_dev(e_cat), off, tune=tab)
+        torch.cuda.synchronize()
+        parts = _split_batch(sizes, off, d_cat, e_cat, w_cat.cpu().numpy(), Z_cat.cpu().numpy())
+        for b in range(0, 48, 6):
+            d, e, w, Z = parts[b]
+            wo, Zo = orc.solve(d, e)
+            check_pairs(d, e, w, Z, wo, Zo)
