@@ -59,7 +59,23 @@ def parse_args(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sections", default="plain,batched,grad,cpu",
                     help="comma list of plain, batched, grad, cpu (plain is always run)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES bytes device to device three times and exit (a copy of known "
+                         "size, to scale the HBM byte counters of a profiler)")
     return ap.parse_args(argv)
+
+
+def copy_calibration(nbytes):
+    import torch
+    n = max(1, nbytes // 8)
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] copied {n * 8} bytes three times")
+    return 0
 
 
 def tree_source_digest() -> str:
@@ -282,6 +298,8 @@ def cpu_baseline(k=400):
 
 def main(argv=None):
     args = parse_args(argv)
+    if args.copy_calibration > 0:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path; use --gpus 1", file=sys.stderr)
         return 2
