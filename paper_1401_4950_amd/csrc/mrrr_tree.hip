@@ -95,12 +95,6 @@ DEV double dq(double num, const Recip& x) {
     return G ? num / x.b : quot(x, num);
 }
 
-DEV uint64_t ld_acq64(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-DEV void st_rel64(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
 DEV int64_t ld_rlx_i64(int64_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -821,60 +815,67 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
 // pos, pos + 1 when it holds that producer's task, pos + cap once consumed.
 
 // Claims tasks at the head of queue q into out[]; returns how many (0 when
-// nothing is published at the head).  One task at a time while the queue is
-// short, so that parallel work spreads over the workers; up to kPopMax
-// consecutive tasks when it holds more than twice the worker count, which
-// divides the traffic on the head counter.  Claimed cells that a pusher has
-// reserved but not yet filled are waited for (pushers fill reserved cells
-// without waiting on anything but the cell itself).
+// the queue is empty).  Head and tail are read together and a claim is tried
+// as soon as the tail is ahead (two device round trips); a failed
+// compare-and-swap returns the current head, so a retry needs no reload.
+// One task per claim while the queue is short, so that parallel work spreads
+// over the workers; about (queued / workers) tasks, up to kPopMax, when it is
+// long, which divides the traffic on the head counter.  Claimed cells that a
+// producer has reserved but not yet published are waited for (producers
+// publish reserved cells without waiting on anything but the cells).
 DEV int try_pop(const Params& P, int q, Task* out) {   // one lane
     // Polling uses relaxed loads only: an acquire at agent scope invalidates
-    // caches, and idle workers poll often.  The acquire fence follows a
-    // successful claim.
+    // the L2, and idle workers poll often.  The acquire follows a claim.
     const uint64_t cap = P.qcap[q];
+    uint64_t pos = __hip_atomic_load(P.ctl->head(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t tl = __hip_atomic_load(P.ctl->tail(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int spin = 0; spin < 64; ++spin) {
-        uint64_t pos = __hip_atomic_load(P.ctl->head(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t cell = pos % cap;
-        const uint64_t sq = __hip_atomic_load(&P.seq[q][cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (sq == pos + 1) {
-            const uint64_t tl = __hip_atomic_load(P.ctl->tail(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t k = 1;
-            if (tl > pos) {
-                const uint64_t share = (tl - pos) / (2 * (uint64_t)P.nworkers);
-                k = share < 1 ? 1 : (share > (uint64_t)kPopMax ? (uint64_t)kPopMax : share);
-            }
-            if (__hip_atomic_compare_exchange_strong(P.ctl->head(q), &pos, pos + k, __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                __atomic_thread_fence(__ATOMIC_ACQUIRE);
-                int got = 0;
-                for (uint64_t i = 0; i < k; ++i) {
-                    const uint64_t c = (pos + i) % cap;
-                    int wait = 0;
-                    while (ld_acq64(&P.seq[q][c]) != pos + i + 1) {
-                        if (++wait > (1 << 24)) {
-                            set_error(P, kErrInternal);
-                            return got;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                    }
-                    out[got++] = P.q[q][c];
-                    st_rel64(&P.seq[q][c], pos + i + cap);
-                }
-                return got;
-            }
-        } else if (sq < pos + 1) {
-            return 0;   // nothing published at the head
+        if (tl <= pos) {
+            tl = __hip_atomic_load(P.ctl->tail(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tl <= pos) return 0;
         }
+        const uint64_t avail = tl - pos;
+        uint64_t k = (avail + (uint64_t)P.nworkers - 1) / (uint64_t)P.nworkers;
+        k = k < 1 ? 1 : (k > (uint64_t)kPopMax ? (uint64_t)kPopMax : k);
+        if (k > 1 && avail < 2 * (uint64_t)P.nworkers) k = 1;
+        if (__hip_atomic_compare_exchange_strong(P.ctl->head(q), &pos, pos + k, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            // every claimed cell published (relaxed polls), then one
+            // acquire for the cells and the data their tasks refer to
+            for (uint64_t i = 0; i < k; ++i) {
+                const uint64_t c = (pos + i) % cap;
+                int wait = 0;
+                while (__hip_atomic_load(&P.seq[q][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos + i + 1) {
+                    if (++wait > (1 << 24)) {
+                        set_error(P, kErrInternal);
+                        return 0;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            for (uint64_t i = 0; i < k; ++i) out[i] = P.q[q][(pos + i) % cap];
+            // the cells go back to the producers once the loads are done
+            __builtin_amdgcn_s_waitcnt(0);
+            for (uint64_t i = 0; i < k; ++i)
+                __hip_atomic_store(&P.seq[q][(pos + i) % cap], pos + i + cap, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            return (int)k;
+        }
+        // pos now holds the current head
     }
     return 0;
 }
 
-// Lane 0 reserves `count` tickets; every lane fills some of the cells.
+// Lane 0 reserves `count` tickets; every lane fills some of the cells.  One
+// agent-scope release after all cells are written publishes them together
+// with everything this wave wrote before (a release writes back the XCD's L2,
+// so it is paid once per push, not once per cell); the sequence numbers then
+// go out as relaxed stores.
 template <class Gen>
 DEV bool push_batch(const Params& P, int q, int count, Gen gen) {
     if (count <= 0) return true;
     const int l = lane_id();
-    __threadfence();   // publish everything this wave wrote before the tasks
     uint64_t first = 0;
     if (l == 0) {
         __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -889,7 +890,7 @@ DEV bool push_batch(const Params& P, int q, int count, Gen gen) {
         const uint64_t cell = pos % cap;
         // wait until the cell is free for this ticket (bounded)
         int spin = 0;
-        while (ld_acq64(&P.seq[q][cell]) != pos) {
+        while (__hip_atomic_load(&P.seq[q][cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos) {
             if (++spin > (1 << 22) || __hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
                 ok = false;
                 break;
@@ -898,7 +899,13 @@ DEV bool push_batch(const Params& P, int q, int count, Gen gen) {
         }
         if (!ok) break;
         P.q[q][cell] = gen(k);
-        st_rel64(&P.seq[q][cell], pos + 1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (ok) {
+        for (int k = l; k < count; k += kWave) {
+            const uint64_t pos = first + (uint64_t)k;
+            __hip_atomic_store(&P.seq[q][pos % cap], pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     if (__ballot(!ok) != 0ull) {
         set_error(P, kErrNoMem);
@@ -1269,7 +1276,9 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         Dr[i] = Dr[i] * (1.0 + amp * unit_pm1(P.seed, 2 * g));
         if (i < n - 1) Lr[i] = Lr[i] * (1.0 + amp * unit_pm1(P.seed, 2 * g + 1));
     }
-    __threadfence();
+    // this wave reads the perturbed rows next; other workers get them through
+    // the release of the pushes below
+    __threadfence_block();
     __syncthreads();
     // root brackets: the definite root's spectrum lies between 0 and the
     // shifted Gershgorin end; confirm both ends by counts, widen if needed
@@ -1366,16 +1375,14 @@ DEV void task_refine(Shared& S, const Params& P, int node_id, int a, int braw, i
             P.w[pr.woff + col] = nd.sigma + (S.m_lo[l] + 0.5 * (S.m_hi[l] - S.m_lo[l]));
         }
     }
-    __threadfence();
+    // the slice's writes go out with the count (release); the last slice
+    // sees every other slice's writes (acquire)
     int last = 0;
     if (l == 0)
         last = (__hip_atomic_fetch_add(&P.nodes[node_id].pending, -1, __ATOMIC_ACQ_REL,
                                        __HIP_MEMORY_SCOPE_AGENT) == 1) ? 1 : 0;
     last = __shfl(last, 0);
-    if (last && mode == kModeClass) {
-        __threadfence();
-        classify(S, P, node_id);
-    }
+    if (last && mode == kModeClass) classify(S, P, node_id);
 }
 
 DEV double grow_lo(double x, double nu) { return x - nu * fabs(x); }
@@ -1721,7 +1728,6 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
         // tasks claimed before an error still count as finished below
         for (int bi = 0; bi < ngot; ++bi) {
             const Task tk = S.task[bi];
-            __threadfence();
             const uint64_t ts = wall_clock64();
             if (l == 0) {
                 S.info_i[0] = 0; S.info_i[1] = 0; S.info_i[2] = -1; S.info_i[3] = 0;
@@ -1737,7 +1743,6 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
                     default: set_error(P, kErrInternal); break;
                 }
             }
-            __threadfence();
             __syncthreads();
             if (P.trace && l == 0 && status == 1) {
                 const int64_t k = __hip_atomic_fetch_add(&P.ctl->trace_top, (int64_t)1, __ATOMIC_RELAXED,
@@ -1761,8 +1766,10 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
             }
             ++ntask;
         }
+        // pending only detects the end of the work (a task's results reach
+        // other workers through the pushes and node counters above)
         if (l == 0 && ngot > 0)
-            __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)-ngot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)-ngot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (status != 1) break;
     }
     add_stat(&P.ctl->qd_steps, steps);
