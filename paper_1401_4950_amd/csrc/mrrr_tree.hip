@@ -72,17 +72,6 @@ DEV double quot(const Recip& x, double a) {
     const double rem = __builtin_fma(-x.b, q1, a);
     return __builtin_fma(rem, x.r, q1);
 }
-// qd_q through the reciprocal: exact IEEE-and-guard fallback on NaN
-DEV double qd_qf(double num, const Recip& x) {
-    double q = quot(x, num);
-    if (__builtin_expect(__builtin_isnan(q), 0)) q = qd_q(num, x.b);
-    return q;
-}
-DEV double divf(double num, const Recip& x) {
-    double q = quot(x, num);
-    if (__builtin_expect(__builtin_isnan(q), 0)) q = num / x.b;
-    return q;
-}
 // Whole-pass forms: G = false takes the reciprocal quotient with no per-row
 // test (the caller checks for a NaN once the pass is over and then runs the
 // pass again with G = true, the IEEE quotient and the guard).
@@ -166,6 +155,8 @@ struct alignas(32) QRow {
 typedef double dv2 __attribute__((ext_vector_type(2)));
 // (d, dll) of staged row k in one 16-byte LDS read
 #define QROW_DDLL(S, k) (*reinterpret_cast<const dv2*>(&(S).tr[(k)].d))
+// rows of three values read ahead of the recurrence (registers for two groups)
+constexpr int kAhead = 4;
 
 struct Shared {
     QRow tr[kTile];                           // staged rows
@@ -315,7 +306,10 @@ DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, dou
 
 // NegCount(T, sigma) for one shift per lane (App. B, Alg. B.1), IEEE form:
 // a zero pivot turns the next one into -inf and the count stays right.
-DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, double sigma) {
+// G = false uses the reciprocal quotient, under which a zero or infinite
+// pivot leaves a NaN instead; negcount_T then repeats the pass in IEEE form.
+template <bool G>
+DEV int negcount_T_impl(Shared& S, const double* d, const double* e, int64_t n, double sigma, bool* bad) {
     double piv = 1.0;
     int cnt = 0;
     RepRow f = T_fetch(d, e, 0, n);
@@ -326,11 +320,22 @@ DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, doubl
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
             const dv2 x = QROW_DDLL(S, t);
-            piv = (i == 0) ? (x.x - sigma) : ((x.x - sigma) - x.y / piv);
+            piv = (i == 0) ? (x.x - sigma) : ((x.x - sigma) - (G ? x.y / piv : quot(recip(piv), x.y)));
             cnt += sbit(piv);
         }
     }
+    *bad = __builtin_isnan(piv);
     return cnt;
+}
+DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, double sigma) {
+    bool bad = false;
+    int c = negcount_T_impl<false>(S, d, e, n, sigma, &bad);
+    if (wave_or(bad ? 1 : 0)) {
+        bool b2 = false;
+        const int c2 = negcount_T_impl<true>(S, d, e, n, sigma, &b2);
+        if (bad) c = c2;
+    }
+    return c;
 }
 
 // ----------------------------------------------------- multisection engine
@@ -534,29 +539,46 @@ template <bool G>
 DEV TwistOut twisted_impl(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
                           const CkPtr& ck, int64_t& steps) {
     TwistOut o;
-    // ---- forward: dstqds with checkpoints of (s, h)
+    // ---- forward: dstqds with checkpoints of (s, h); rows read from LDS
+    //      in groups of kAhead, one group ahead of the arithmetic
     double s = -lam, h = 1.0, dplast = 0.0;
     int cnt = 0;
+    auto row = [&](int64_t i, const QRow& x) {
+        if ((i & (kCkb - 1)) == 0 && live) {
+            ck.at(i / kCkb, 0) = s;
+            ck.at(i / kCkb, 1) = h;
+        }
+        const double dp = s + x.d;
+        cnt += sbit(dp);
+        const Recip rc = recip(dp);
+        const double q = qq<G>(s, rc);
+        const double lp = dq<G>(x.dl, rc);
+        h = 1.0 + (lp * lp) * h;
+        dplast = dp;
+        s = q * x.dll - lam;
+    };
     RepRow f = rep_fetch(D, L, 0, n);
     for (int64_t base = 0; base < n; base += kTile) {
         rep_commit(S, f);
         if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
-        for (int t = 0; t < lim; ++t) {
-            const int64_t i = base + t;
-            if ((i & (kCkb - 1)) == 0 && live) {
-                ck.at(i / kCkb, 0) = s;
-                ck.at(i / kCkb, 1) = h;
+        if (lim == kTile) {
+            QRow cur[kAhead], nxt[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) cur[u] = S.tr[u];
+#pragma unroll
+            for (int g = 0; g < kTile / kAhead; ++g) {
+                if (g + 1 < kTile / kAhead) {
+#pragma unroll
+                    for (int u = 0; u < kAhead; ++u) nxt[u] = S.tr[(g + 1) * kAhead + u];
+                }
+#pragma unroll
+                for (int u = 0; u < kAhead; ++u) row(base + g * kAhead + u, cur[u]);
+#pragma unroll
+                for (int u = 0; u < kAhead; ++u) cur[u] = nxt[u];
             }
-            const QRow x = S.tr[t];
-            const double dp = s + x.d;
-            cnt += sbit(dp);
-            const Recip rc = recip(dp);
-            const double q = qq<G>(s, rc);
-            const double lp = dq<G>(x.dl, rc);
-            h = 1.0 + (lp * lp) * h;
-            dplast = dp;
-            s = q * x.dll - lam;
+        } else {
+            for (int t = 0; t < lim; ++t) row(base + t, S.tr[t]);
         }
     }
     steps += n;
@@ -980,32 +1002,52 @@ struct FacOut {
 };
 
 // L+ D+ L+^T = L D L^T - tau I by the differential stationary qd transform
-// (Alg. 3.5), one shift per active lane, written to (Dp, Lp).  ok = the
-// factorisation exists (all pivots finite and nonzero); growth = ||D+||_max.
+// (Alg. 3.5), one shift per lane, written to (Dp, Lp) by the `act` lanes.
+// ok = the factorisation exists (all pivots finite and nonzero); growth =
+// ||D+||_max.  Quotients come from the reciprocal with no per-row test: a
+// zero or infinite pivot makes the IEEE form fail `ok`, and turns the
+// reciprocal form into NaN, which fails it too, so both forms accept the
+// same candidates and a failed candidate is never used.  Rows are read from
+// LDS in groups of kAhead, one group ahead of the arithmetic.
 DEV FacOut dstqds(Shared& S, const double* D, const double* L, int64_t n, double tau, bool act,
                   double* Dp, double* Lp) {
     double s = -tau, gmax = 0.0;
     int ok = 1;
+    auto row = [&](int64_t i, const QRow& x) {
+        const double dp = s + x.d;
+        if (act) Dp[i] = dp;
+        ok &= (__builtin_isfinite(dp) && dp != 0.0) ? 1 : 0;
+        gmax = fmax(gmax, fabs(dp));
+        // the last row has dl = dll = 0 (rep_fetch): lp = 0 there, and
+        // Lp[n-1] lies inside the 2n-double block of the representation
+        const Recip rc = recip(dp);
+        const double lp = quot(rc, x.dl);
+        if (act) Lp[i] = lp;
+        ok &= __builtin_isfinite(lp) ? 1 : 0;
+        s = quot(rc, s) * x.dll - tau;
+    };
     RepRow f = rep_fetch(D, L, 0, n);
     for (int64_t base = 0; base < n; base += kTile) {
         rep_commit(S, f);
         if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
-#pragma unroll 4
-        for (int t = 0; t < lim; ++t) {
-            const int64_t i = base + t;
-            const QRow x = S.tr[t];
-            const double dp = s + x.d;
-            if (act) Dp[i] = dp;
-            ok &= (__builtin_isfinite(dp) && dp != 0.0) ? 1 : 0;
-            gmax = fmax(gmax, fabs(dp));
-            // the last row has dl = dll = 0 (rep_fetch): lp = 0 there, and
-            // Lp[n-1] lies inside the 2n-double block of the representation
-            const Recip rc = recip(dp);
-            const double lp = divf(x.dl, rc);
-            if (act) Lp[i] = lp;
-            ok &= __builtin_isfinite(lp) ? 1 : 0;
-            s = qd_qf(s, rc) * x.dll - tau;
+        if (lim == kTile) {
+            QRow cur[kAhead], nxt[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) cur[u] = S.tr[u];
+#pragma unroll
+            for (int g = 0; g < kTile / kAhead; ++g) {
+                if (g + 1 < kTile / kAhead) {
+#pragma unroll
+                    for (int u = 0; u < kAhead; ++u) nxt[u] = S.tr[(g + 1) * kAhead + u];
+                }
+#pragma unroll
+                for (int u = 0; u < kAhead; ++u) row(base + g * kAhead + u, cur[u]);
+#pragma unroll
+                for (int u = 0; u < kAhead; ++u) cur[u] = nxt[u];
+            }
+        } else {
+            for (int t = 0; t < lim; ++t) row(base + t, S.tr[t]);
         }
     }
     FacOut o;
