@@ -315,7 +315,7 @@ Sizes base_sizes(int64_t rows, int64_t nprob, int64_t kwork, int64_t nmax, doubl
     sz.qcap[kQSingle] = (uint64_t)std::max<int64_t>(16384, rows + 1024);
     // node pool: 4 n doubles per representation (two shift candidates of
     // D and L); start from a few hundred nodes of the largest block size
-    const double nodes = std::min<double>((double)kwork + 2.0 * nprob, 256.0 + (double)kwork / 8.0);
+    const double nodes = std::min<double>((double)kwork + 2.0 * nprob, 256.0 + (double)kwork / 4.0);
     double a = 4.0 * (double)nmax * std::max(nodes, 8.0 * nprob) * std::max(arena_scale, 1e-3);
     const double cap = 4.0 * (double)nmax * ((double)kwork + 2.0 * nprob + 8.0) * std::max(1.0, arena_scale);
     if (a > cap) a = cap;

@@ -1972,7 +1972,8 @@ extern "C" __global__ __launch_bounds__(1024) void mrrr_sort_kernel(Params P) {
     Problem* prp = P.probs + blockIdx.x;
     const int64_t m = prp->m;
     const int tid = threadIdx.x, nt = blockDim.x;
-    if (m < 2) return;
+    // a solve that failed (and will be retried or reported) has no output
+    if (m < 2 || __hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     double* w = P.w + prp->woff;
     if (tid == 0) unsorted = 0;
     __syncthreads();
@@ -2011,26 +2012,52 @@ extern "C" __global__ __launch_bounds__(1024) void mrrr_sort_kernel(Params P) {
     if (tid == 0) prp->flags |= 2;
 }
 
+// Cycle leaders of a marked problem's permutation by pointer jumping: after
+// round 0 (lead = p, jump = col[p]) each round sets lead = min(lead,
+// lead[jump]) and jump = jump[jump], so after ceil(log2 m) rounds lead[p] is
+// the smallest index on p's cycle -- O(m log m) work whatever the cycle
+// lengths (the columns of split blocks interleave into long cycles).  Two
+// buffers of (lead, jump) alternate in the colbuf scratch, which the sort's
+// keys no longer need: int32 at colbuf + 16 row0 bytes, 4 m entries.
+DEV int32_t* cycle_buf(const Params& P, const Problem& pr, int which) {   // which: 0 = A, 1 = B
+    return reinterpret_cast<int32_t*>(P.colbuf) + 4 * pr.row0 + 2 * pr.m * which;
+}
+
+extern "C" __global__ __launch_bounds__(256) void mrrr_cycle_kernel(Params P, int round) {
+    const Problem pr = P.probs[blockIdx.y];
+    if (!(pr.flags & 2) || !P.jobz) return;
+    const int64_t m = pr.m;
+    const int32_t* col = P.perm + 2 * pr.row0;
+    int32_t* src = cycle_buf(P, pr, (round & 1) ? 0 : 1);   // round r reads the buffer round r-1 wrote
+    int32_t* dst = cycle_buf(P, pr, (round & 1) ? 1 : 0);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+        if (round == 0) {
+            dst[p] = (int32_t)p;
+            dst[m + p] = col[p];
+        } else {
+            const int32_t jp = src[m + p];
+            const int32_t a = src[p], b = src[jp];
+            dst[p] = a < b ? a : b;
+            dst[m + p] = src[m + jp];
+        }
+    }
+}
+
 // Position i of a marked problem receives column col[i].  The permutation is
 // applied in place cycle by cycle: the wave that holds a cycle's smallest
-// index moves it, 512 rows at a time through registers.
-extern "C" __global__ __launch_bounds__(64) void mrrr_permute_kernel(Params P) {
+// index (its leader, from mrrr_cycle_kernel) moves it, 512 rows at a time
+// through registers.
+extern "C" __global__ __launch_bounds__(64) void mrrr_permute_kernel(Params P, int rounds) {   // rounds: index of the last round
     constexpr int kR = 8;
     const int l = lane_id();
     const Problem pr = P.probs[blockIdx.y];
     if (!(pr.flags & 2) || !P.jobz) return;
     const int64_t m = pr.m, n = pr.n, ldz = pr.ldz;
     const int32_t* col = P.perm + 2 * pr.row0;
+    const int32_t* lead = cycle_buf(P, pr, (rounds & 1) ? 1 : 0);   // written by round `rounds`
     double* Z = P.Z + pr.zoff;
     for (int64_t p = blockIdx.x; p < m; p += gridDim.x) {
-        if (col[p] == p) continue;
-        bool leader = true;
-        int64_t q = col[p];
-        for (int64_t guard = 0; q != p; ++guard) {
-            if (q < p || guard > m) { leader = false; break; }
-            q = col[q];
-        }
-        if (!leader) continue;
+        if (col[p] == p || lead[p] != p) continue;
         for (int64_t r0 = 0; r0 < n; r0 += kWave * kR) {
             double keep[kR];
 #pragma unroll
@@ -2064,6 +2091,7 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_permute_kernel(Params P) {
 // (ties to the lowest row).  One wavefront per column.
 extern "C" __global__ __launch_bounds__(64) void mrrr_sign_kernel(Params P, int64_t ncols_total) {
     const int l = lane_id();
+    if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     for (int64_t g = blockIdx.x; g < ncols_total; g += gridDim.x) {
         // column g is slot-ordered: find its problem
         int a = 0, b = P.nprob - 1;
@@ -2118,8 +2146,13 @@ hipError_t launch_tree(const Params& P, hipStream_t s) {
 
 hipError_t launch_finalize(const Params& P, hipStream_t s) {
     hipLaunchKernelGGL(mrrr_sort_kernel, dim3(P.nprob), dim3(1024), 0, s, P);
+    // rounds of pointer jumping: enough for the longest possible cycle
+    int rounds = 1;
+    while ((int64_t)1 << (rounds - 1) < std::max<int64_t>(P.total_rows, 2)) ++rounds;
+    const unsigned gc = (unsigned)std::max(1, std::min(256, 65536 / std::max(1, (int)P.nprob)));
+    for (int r = 0; r < rounds; ++r) hipLaunchKernelGGL(mrrr_cycle_kernel, dim3(gc, P.nprob), dim3(256), 0, s, P, r);
     const unsigned gx = (unsigned)std::max(1, std::min(512, 65536 / std::max(1, (int)P.nprob)));
-    hipLaunchKernelGGL(mrrr_permute_kernel, dim3(gx, P.nprob), dim3(kWave), 0, s, P);
+    hipLaunchKernelGGL(mrrr_permute_kernel, dim3(gx, P.nprob), dim3(kWave), 0, s, P, rounds - 1);
     return hipGetLastError();
 }
 

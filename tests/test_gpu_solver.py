@@ -235,3 +235,18 @@ def test_config3_subset_n50000(orc, fam):
     assert np.max(np.abs(wh[idx - 1] - wo)) <= 4 * n * EPS * tn
     res, orth = gpu_residual_orth(d, e, w, Z, tn)
     assert res <= 10 and orth <= 100, (res, orth)
+
+
+def test_split_blocks_with_interleaved_spectra(orc):
+    """Two blocks whose eigenvalues interleave: the final merge permutes the
+    columns along long cycles."""
+    d1, e1 = ti.random_uniform(500, 21)
+    d = np.concatenate([d1, d1 + 1e-4])
+    e = np.concatenate([e1, [0.0], e1])
+    w, Z = gpu_solve(d, e)
+    wo, Zo = orc.solve(d, e)
+    check_pairs(d, e, w, Z, wo, Zo)
+    # every column lives on one block
+    top = np.abs(Z[:500]).max(axis=0) > 0
+    bot = np.abs(Z[500:]).max(axis=0) > 0
+    assert not np.any(top & bot)
