@@ -195,7 +195,9 @@ DEV RepRow rep_fetch(const double* D, const double* L, int64_t base, int64_t n) 
     return f;
 }
 
-DEV void rep_commit(Shared& S, const RepRow& f) {
+// Returns whether the lane's row is in the range the division-free count
+// accepts (kHomData below); the other callers ignore it.
+DEV bool rep_commit(Shared& S, const RepRow& f) {
     const int l = lane_id();
     const double dl = f.d * f.l;
     __syncthreads();
@@ -206,6 +208,8 @@ DEV void rep_commit(Shared& S, const RepRow& f) {
     x.pad = 0.0;
     S.tr[l] = x;
     __syncthreads();
+    return (f.d == 0.0 && f.l == 0.0) ||
+           (fabs(x.d) >= 0x1p-150 && (f.l == 0.0 || fabs(x.dll) >= 0x1p-150));
 }
 
 // Rows of T (row i couples to row i-1).
@@ -221,7 +225,9 @@ DEV RepRow T_fetch(const double* d, const double* e, int64_t base, int64_t n) {
     return f;
 }
 
-DEV void T_commit(Shared& S, const RepRow& f) {
+// Returns whether the lane's row is in the range the division-free count
+// accepts (as rep_commit).
+DEV bool T_commit(Shared& S, const RepRow& f) {
     const int l = lane_id();
     __syncthreads();
     QRow x;
@@ -231,6 +237,7 @@ DEV void T_commit(Shared& S, const RepRow& f) {
     x.pad = 0.0;
     S.tr[l] = x;
     __syncthreads();
+    return (f.d == 0.0 || fabs(f.d) >= 0x1p-150) && (f.l == 0.0 || fabs(x.dll) >= 0x1p-150);
 }
 
 // ------------------------------------------------------------ Sturm counts
@@ -255,61 +262,108 @@ DEV int negcount_rep_guarded(Shared& S, const double* D, const double* L, int64_
     return cnt;
 }
 
-// The same count with the reciprocal quotient and no guard.  The guard
-// matters only after a pivot was zero or infinite, and every such case
-// leaves a NaN that persists to the end of the pass (inf/inf, 0*inf and any
-// arithmetic on a NaN give NaN), so a final NaN sends the wave through the
-// guarded pass again.  Rows are read from LDS eight at a time, one group
-// ahead of the arithmetic, so that LDS latency stays off the recurrence.
+// The same count without divisions.  With s_i = u_i / v_i the recurrence of
+// Alg. B.2 reads
+//     w_i = d_i v_i + u_i            (d+_i = w_i / v_i)
+//     u_{i+1} = u_i (d_i l_i^2) - sigma w_i,   v_{i+1} = w_i,
+// so that sign(d+_i) = sign(w_i) xor sign(w_{i-1}) (v_0 = 1, u_0 = -sigma).
+// Each quantity carries one rounding as in the quotient form (one fewer: there
+// is no quotient), so the count is that of the same nearby representation the
+// error analysis of the stationary transform allows.  The pair (u, v) is
+// scaled by a power of two every 8 rows, which changes no sign and no
+// rounding.  The relative-error argument needs every rounded result to be
+// normal or an exact zero; it holds when the data and sigma are at least
+// kHomData in magnitude (or zero) and every u, w met is at least kHomState
+// (then every exact result is a multiple of 2^-1074, so a zero is exact and a
+// nonzero result is caught by the check if it is tiny).  A lane outside these
+// bounds, or with a non-finite (u, v) at the end, counts again with the
+// guarded quotient form.  One row costs two dependent fused multiply-adds
+// instead of a reciprocal and four corrections; the sign bits of 32 rows are
+// shifted into one word and counted with one popcount.
+constexpr double kHomData = 0x1p-150;
+constexpr double kHomState = 0x1p-800;
+
+DEV unsigned hi32(double x) { return (unsigned)((unsigned long long)__double_as_longlong(x) >> 32); }
+
+DEV void hom_rescale(double& u, double& v, double& mw) {
+    const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(u), fabs(v)));
+    u = __builtin_ldexp(u, -ex);
+    v = __builtin_ldexp(v, -ex);
+    mw = fmin(mw, fabs(v));
+}
+
 DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, double sigma) {
-    double s = -sigma;
+    double u = -sigma, v = 1.0;
+    double mw = 1.0, mu = 1.0;   // smallest |w| and |u| met
+    unsigned B = 0, Bold = 0;    // sign bits of the last rows, newest in bit 0
     int cnt = 0;
+    bool data_ok = true;
     RepRow f = rep_fetch(D, L, 0, n);
     for (int64_t base = 0; base < n; base += kTile) {
-        rep_commit(S, f);
+        data_ok &= (__ballot(!rep_commit(S, f)) == 0ull);
         if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         if (lim == kTile) {
             dv2 cur[8], nxt[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) cur[u] = QROW_DDLL(S, u);
+            for (int k = 0; k < 8; ++k) cur[k] = QROW_DDLL(S, k);
 #pragma unroll
             for (int g = 0; g < kTile / 8; ++g) {
                 if (g + 1 < kTile / 8) {
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) nxt[u] = QROW_DDLL(S, (g + 1) * 8 + u);
+                    for (int k = 0; k < 8; ++k) nxt[k] = QROW_DDLL(S, (g + 1) * 8 + k);
                 }
+                // keep the next group's LDS reads ahead of this group's rows
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const double dp = s + cur[u].x;
-                    cnt += sbit(dp);
-                    s = quot(recip(dp), s) * cur[u].y - sigma;
+                for (int k = 0; k < 8; ++k) {
+                    const double w = __builtin_fma(cur[k].x, v, u);
+                    const double p = u * cur[k].y;
+                    B = __builtin_amdgcn_alignbit(B, hi32(w), 31);
+                    mu = fmin(mu, fabs(u));
+                    u = __builtin_fma(-sigma, w, p);
+                    v = w;
+                    mw = fmin(mw, fabs(w));
                 }
+                if ((g & 3) == 3) {
+                    // 32 sign bits: a sign change between neighbouring rows
+                    // (and between the block's first row and the row before)
+                    cnt += __builtin_popcount(B ^ __builtin_amdgcn_alignbit(Bold, B, 1));
+                    Bold = B;
+                }
+                hom_rescale(u, v, mw);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+                for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
             }
         } else {
             for (int t = 0; t < lim; ++t) {
                 const dv2 x = QROW_DDLL(S, t);
-                const double dp = s + x.x;
-                cnt += sbit(dp);
-                s = quot(recip(dp), s) * x.y - sigma;
+                const double w = __builtin_fma(x.x, v, u);
+                cnt += sbit(w) ^ sbit(v);
+                const double p = u * x.y;
+                mu = fmin(mu, fabs(u));
+                u = __builtin_fma(-sigma, w, p);
+                v = w;
+                mw = fmin(mw, fabs(w));
+                hom_rescale(u, v, mw);
             }
         }
     }
-    if (wave_or(__builtin_isnan(s) ? 1 : 0)) {
+    // sigma = 0 keeps u = 0 exactly (then w_i = d_i v_i); otherwise a zero u
+    // is an exact zero too but is sent to the guarded form with the tiny ones
+    const bool sig_ok = sigma == 0.0 || fabs(sigma) >= kHomData;
+    const bool bad = !data_ok || !sig_ok || !(mw >= kHomState) || (sigma != 0.0 && !(mu >= kHomState)) ||
+                     !__builtin_isfinite(u) || !__builtin_isfinite(v);
+    if (wave_or(bad ? 1 : 0)) {
         const int c2 = negcount_rep_guarded(S, D, L, n, sigma);
-        if (__builtin_isnan(s)) cnt = c2;
+        if (bad) cnt = c2;
     }
     return cnt;
 }
 
 // NegCount(T, sigma) for one shift per lane (App. B, Alg. B.1), IEEE form:
 // a zero pivot turns the next one into -inf and the count stays right.
-// G = false uses the reciprocal quotient, under which a zero or infinite
-// pivot leaves a NaN instead; negcount_T then repeats the pass in IEEE form.
-template <bool G>
-DEV int negcount_T_impl(Shared& S, const double* d, const double* e, int64_t n, double sigma, bool* bad) {
+DEV int negcount_T_ieee(Shared& S, const double* d, const double* e, int64_t n, double sigma) {
     double piv = 1.0;
     int cnt = 0;
     RepRow f = T_fetch(d, e, 0, n);
@@ -320,22 +374,83 @@ DEV int negcount_T_impl(Shared& S, const double* d, const double* e, int64_t n, 
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
             const dv2 x = QROW_DDLL(S, t);
-            piv = (i == 0) ? (x.x - sigma) : ((x.x - sigma) - (G ? x.y / piv : quot(recip(piv), x.y)));
+            piv = (i == 0) ? (x.x - sigma) : ((x.x - sigma) - x.y / piv);
             cnt += sbit(piv);
         }
     }
-    *bad = __builtin_isnan(piv);
     return cnt;
 }
+
+// The same count without divisions: with the leading minors P_i of T - sigma I
+// (P_{-1} = 1, P_{-2} = 0) the pivots of Alg. B.1 are q_i = P_i / P_{i-1} and
+//     P_i = (alpha_i - sigma) P_{i-1} - beta_{i-1}^2 P_{i-2},
+// one fused multiply-add on the dependence chain per row.  The roundings are
+// those of the pivot form (the difference, the product with beta^2, the final
+// subtraction), with the quotient's rounding gone; (P_{i-1}, P_{i-2}) is
+// scaled by a power of two every 8 rows, and the same bounds as for
+// negcount_rep (data, sigma, every P met) keep every rounded result normal or
+// an exact zero -- the difference alpha_i - sigma is exact or rounded with a
+// last bit no finer than 2^-202, so its products stay on the 2^-1074 grid.
+// A lane outside them counts again in IEEE form.
 DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, double sigma) {
-    bool bad = false;
-    int c = negcount_T_impl<false>(S, d, e, n, sigma, &bad);
-    if (wave_or(bad ? 1 : 0)) {
-        bool b2 = false;
-        const int c2 = negcount_T_impl<true>(S, d, e, n, sigma, &b2);
-        if (bad) c = c2;
+    double a = 1.0, b = 0.0;     // P_{i-1}, P_{i-2}
+    double mw = 1.0;
+    unsigned B = 0, Bold = 0;
+    int cnt = 0;
+    bool data_ok = true;
+    RepRow f = T_fetch(d, e, 0, n);
+    for (int64_t base = 0; base < n; base += kTile) {
+        data_ok &= (__ballot(!T_commit(S, f)) == 0ull);
+        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n);
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        if (lim == kTile) {
+            dv2 cur[8], nxt[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cur[k] = QROW_DDLL(S, k);
+#pragma unroll
+            for (int g = 0; g < kTile / 8; ++g) {
+                if (g + 1 < kTile / 8) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) nxt[k] = QROW_DDLL(S, (g + 1) * 8 + k);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const double c = cur[k].x - sigma;
+                    const double m = cur[k].y * b;
+                    const double pn = __builtin_fma(c, a, -m);
+                    B = __builtin_amdgcn_alignbit(B, hi32(pn), 31);
+                    b = a;
+                    a = pn;
+                    mw = fmin(mw, fabs(pn));
+                }
+                if ((g & 3) == 3) {
+                    cnt += __builtin_popcount(B ^ __builtin_amdgcn_alignbit(Bold, B, 1));
+                    Bold = B;
+                }
+                hom_rescale(a, b, mw);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+            }
+        } else {
+            for (int t = 0; t < lim; ++t) {
+                const dv2 x = QROW_DDLL(S, t);
+                const double pn = __builtin_fma(x.x - sigma, a, -(x.y * b));
+                cnt += sbit(pn) ^ sbit(a);
+                b = a;
+                a = pn;
+                mw = fmin(mw, fabs(pn));
+                hom_rescale(a, b, mw);
+            }
+        }
     }
-    return c;
+    const bool sig_ok = sigma == 0.0 || fabs(sigma) >= kHomData;
+    const bool bad = !data_ok || !sig_ok || !(mw >= kHomState) || !__builtin_isfinite(a) || !__builtin_isfinite(b);
+    if (wave_or(bad ? 1 : 0)) {
+        const int c2 = negcount_T_ieee(S, d, e, n, sigma);
+        if (bad) cnt = c2;
+    }
+    return cnt;
 }
 
 // ----------------------------------------------------- multisection engine
