@@ -114,7 +114,8 @@ typedef struct {
     int32_t pad;
     int64_t n_unverified_rrr;  /* RRRs accepted without passing the test */
     int64_t n_bisect_fallback; /* singletons that fell back to bisection */
-    int64_t n_nan_retry;       /* recurrences redone after a NaN */
+    int64_t n_nan_retry;       /* twisted-factorisation and eigenvector passes that one
+                                  worker redid in IEEE form after a NaN */
     int64_t qd_steps;          /* lane-steps of the qd / Sturm recurrences */
     int64_t n_tasks;           /* device tasks executed */
     int64_t n_singleton_tasks; /* singleton bundles executed */
@@ -124,6 +125,10 @@ typedef struct {
     double tree_ms;            /* device time of the persistent tree kernel
                                   alone (hipEvents on the handle's stream
                                   around its launch); 0 for batched calls */
+    int64_t n_sturm_guarded;   /* Sturm-count passes that one worker redid in the
+                                  guarded quotient form: a zero pivot, an overflow,
+                                  or data outside the range of the division-free
+                                  count (App. B) */
 } mrrr_stats_t;
 
 /* Creates a handle on HIP device `device`.  The handle owns a workspace that

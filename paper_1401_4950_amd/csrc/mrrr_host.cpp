@@ -343,6 +343,7 @@ void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms, float tree_
     st->n_unverified_rrr = c.n_unverified;
     st->n_bisect_fallback = c.n_fallback;
     st->n_nan_retry = c.n_nan;
+    st->n_sturm_guarded = c.n_sturm;
     st->qd_steps = c.qd_steps;
     st->n_tasks = c.n_tasks;
     st->n_singleton_tasks = c.n_single;

@@ -63,6 +63,8 @@ struct Problem {
     int16_t bundle;   // singletons per S-task
     int32_t slice_max;  // largest refinement slice
     int32_t pad;
+    double tscale;    // device: the tree works on tscale * T (a power of two)
+    double tscale_inv;
 };
 
 struct Block {
@@ -109,6 +111,7 @@ struct Ctl {
     int64_t n_nodes, largest_cluster, n_unverified, n_fallback, n_nan;
     int64_t qd_steps, n_tasks, n_single, n_rqi, n_blocks;
     int64_t trace_top;
+    int64_t n_sturm;
 #ifdef __HIPCC__
     __device__ __host__ uint64_t* head(int q) { return head_ + q * kLineU64; }
     __device__ __host__ uint64_t* tail(int q) { return tail_ + q * kLineU64; }

@@ -173,6 +173,8 @@ struct Shared {
     // what the finished task reports to the trace: depth, flags, child, x0, x1
     int32_t info_i[4];
     double info_d[2];
+    int32_t redo;                             // twisted / Getvec passes redone in IEEE form
+    int32_t redo_sturm;                       // Sturm counts redone in guarded form
 };
 
 // Rows [base, base + 64) of an N-representation (D, L): each lane fetches one
@@ -212,15 +214,16 @@ DEV bool rep_commit(Shared& S, const RepRow& f) {
            (fabs(x.d) >= 0x1p-150 && (f.l == 0.0 || fabs(x.dll) >= 0x1p-150));
 }
 
-// Rows of T (row i couples to row i-1).
-DEV RepRow T_fetch(const double* d, const double* e, int64_t base, int64_t n) {
+// Rows of T (row i couples to row i-1), multiplied by the problem's
+// power-of-two scale (exact; see mrrr_setup_kernel).
+DEV RepRow T_fetch(const double* d, const double* e, int64_t base, int64_t n, double sc) {
     const int64_t r = base + lane_id();
     RepRow f;
     f.d = 0.0;
     f.l = 0.0;
     if (r < n) {
-        f.d = d[r];
-        if (r >= 1) f.l = e[r - 1];
+        f.d = d[r] * sc;
+        if (r >= 1) f.l = e[r - 1] * sc;
     }
     return f;
 }
@@ -357,19 +360,20 @@ DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, dou
     if (wave_or(bad ? 1 : 0)) {
         const int c2 = negcount_rep_guarded(S, D, L, n, sigma);
         if (bad) cnt = c2;
+        if (lane_id() == 0) S.redo_sturm += 1;
     }
     return cnt;
 }
 
 // NegCount(T, sigma) for one shift per lane (App. B, Alg. B.1), IEEE form:
 // a zero pivot turns the next one into -inf and the count stays right.
-DEV int negcount_T_ieee(Shared& S, const double* d, const double* e, int64_t n, double sigma) {
+DEV int negcount_T_ieee(Shared& S, const double* d, const double* e, int64_t n, double sc, double sigma) {
     double piv = 1.0;
     int cnt = 0;
-    RepRow f = T_fetch(d, e, 0, n);
+    RepRow f = T_fetch(d, e, 0, n, sc);
     for (int64_t base = 0; base < n; base += kTile) {
         T_commit(S, f);
-        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n);
+        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n, sc);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
@@ -392,16 +396,16 @@ DEV int negcount_T_ieee(Shared& S, const double* d, const double* e, int64_t n, 
 // an exact zero -- the difference alpha_i - sigma is exact or rounded with a
 // last bit no finer than 2^-202, so its products stay on the 2^-1074 grid.
 // A lane outside them counts again in IEEE form.
-DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, double sigma) {
+DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, double sc, double sigma) {
     double a = 1.0, b = 0.0;     // P_{i-1}, P_{i-2}
     double mw = 1.0;
     unsigned B = 0, Bold = 0;
     int cnt = 0;
     bool data_ok = true;
-    RepRow f = T_fetch(d, e, 0, n);
+    RepRow f = T_fetch(d, e, 0, n, sc);
     for (int64_t base = 0; base < n; base += kTile) {
         data_ok &= (__ballot(!T_commit(S, f)) == 0ull);
-        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n);
+        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n, sc);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         if (lim == kTile) {
             dv2 cur[8], nxt[8];
@@ -447,8 +451,9 @@ DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, doubl
     const bool sig_ok = sigma == 0.0 || fabs(sigma) >= kHomData;
     const bool bad = !data_ok || !sig_ok || !(mw >= kHomState) || !__builtin_isfinite(a) || !__builtin_isfinite(b);
     if (wave_or(bad ? 1 : 0)) {
-        const int c2 = negcount_T_ieee(S, d, e, n, sigma);
+        const int c2 = negcount_T_ieee(S, d, e, n, sc, sigma);
         if (bad) cnt = c2;
+        if (lane_id() == 0) S.redo_sturm += 1;
     }
     return cnt;
 }
@@ -793,6 +798,7 @@ DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, dou
     const bool redo = live && o.bad;
     if (wave_or(redo ? 1 : 0)) {
         const TwistOut g = twisted_impl<true>(S, D, L, n, lam, redo, ck, steps);
+        if (lane_id() == 0) S.redo += 1;
         if (redo) {
             o = g;
             o.guarded = 1;
@@ -941,6 +947,7 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
     if (wave_or(redo ? 1 : 0)) {
         const double sg = solve_vector_impl<true>(S, D, L, n, lam, redo, r, scale, ck, zcol, write, steps);
         if (redo) ss = sg;
+        if (lane_id() == 0) S.redo += 1;
     }
     return ss;
 }
@@ -1174,14 +1181,14 @@ DEV FacOut dstqds(Shared& S, const double* D, const double* L, int64_t n, double
 // T - mu I = L D L^T by Gaussian elimination without pivoting; sgn > 0
 // requires every pivot positive, sgn < 0 every pivot negative (a definite
 // root, Sec. 3.1.2).
-DEV FacOut factor_T(Shared& S, const double* d, const double* e, int64_t n, double mu, int sgn,
+DEV FacOut factor_T(Shared& S, const double* d, const double* e, int64_t n, double sc, double mu, int sgn,
                     bool act, double* Dd, double* Ld) {
     double dprev = 1.0, gmax = 0.0;
     int ok = 1;
-    RepRow f = T_fetch(d, e, 0, n);
+    RepRow f = T_fetch(d, e, 0, n, sc);
     for (int64_t base = 0; base < n; base += kTile) {
         T_commit(S, f);
-        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n);
+        if (base + kTile < n) f = T_fetch(d, e, base + kTile, n, sc);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
@@ -1359,12 +1366,13 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     const int64_t n = blk.n;
     const double* d = P.d + blk.row0;
     const double* e = P.e + blk.row0;
-    // Gershgorin interval of the block (App. B, Alg. B.3)
+    const double sc = P.probs[blk.prob].tscale;
+    // Gershgorin interval of the block (App. B, Alg. B.3), of the scaled T
     double gl = __builtin_inf(), gu = -__builtin_inf();
     for (int64_t i = l; i < n; i += kWave) {
-        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
-        gl = fmin(gl, d[i] - r);
-        gu = fmax(gu, d[i] + r);
+        const double r = (i > 0 ? fabs(e[i - 1] * sc) : 0.0) + (i < n - 1 ? fabs(e[i] * sc) : 0.0);
+        gl = fmin(gl, d[i] * sc - r);
+        gu = fmax(gu, d[i] * sc + r);
     }
     gl = wave_min(gl);
     gu = wave_max(gu);
@@ -1382,7 +1390,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         if (hi1 - lo1 <= delta && hin - lon <= delta) break;
         const double lo = half ? lon : lo1, hi = half ? hin : hi1;
         const double sig = lo + (hi - lo) * (double)(t + 1) / 33.0;
-        const int c = negcount_T(S, d, e, n, sig);
+        const int c = negcount_T(S, d, e, n, sc, sig);
         steps += n * kWave;
         const uint64_t ge = __ballot(c >= (half ? (int)n : 1));
         const uint64_t g0 = ge & 0xffffffffull, g1 = ge >> 32;
@@ -1404,7 +1412,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     int side = -1;
     for (int tr = 0; tr < 16 && side < 0; ++tr) {
         const double mu = (l == 0) ? mul : mur;
-        const FacOut f = factor_T(S, d, e, n, mu, (l == 0) ? 1 : -1, l < 2,
+        const FacOut f = factor_T(S, d, e, n, sc, mu, (l == 0) ? 1 : -1, l < 2,
                                   (l == 0) ? C0 : C1, ((l == 0) ? C0 : C1) + n);
         steps += 2 * n;
         const int ok0 = __shfl(f.ok, 0), ok1 = __shfl(f.ok, 1);
@@ -1529,7 +1537,7 @@ DEV void task_refine(Shared& S, const Params& P, int node_id, int a, int braw, i
         if (j >= blk.w0 && j <= blk.w1) {
             const Problem& pr = P.probs[blk.prob];
             const int64_t col = blk.col0 + (j - blk.w0);
-            P.w[pr.woff + col] = nd.sigma + (S.m_lo[l] + 0.5 * (S.m_hi[l] - S.m_lo[l]));
+            P.w[pr.woff + col] = (nd.sigma + (S.m_lo[l] + 0.5 * (S.m_hi[l] - S.m_lo[l]))) * pr.tscale_inv;
         }
     }
     // the slice's writes go out with the count (release); the last slice
@@ -1837,7 +1845,7 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
             for (int64_t i = r0 + n; i < pr.n; ++i) zc[i] = 0.0;
         }
     }
-    if (act) P.w[pr.woff + col] = nd.sigma + lam;
+    if (act) P.w[pr.woff + col] = (nd.sigma + lam) * pr.tscale_inv;
     add_stat(&P.ctl->n_rqi, nrqi);
     add_stat(&P.ctl->n_fallback, nfb);
 }
@@ -1855,6 +1863,10 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
     const int l = lane_id();
     const uint64_t t0 = wall_clock64();
     int64_t steps = 0, ntask = 0, nsingle = 0;
+    if (l == 0) {
+        S.redo = 0;
+        S.redo_sturm = 0;
+    }
     for (;;) {
         if (l == 0) {
             int status = 0, got = 0;
@@ -1932,6 +1944,8 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
     add_stat(&P.ctl->qd_steps, steps);
     add_stat(&P.ctl->n_tasks, ntask);
     add_stat(&P.ctl->n_single, nsingle);
+    add_stat(&P.ctl->n_nan, (int64_t)S.redo);
+    add_stat(&P.ctl->n_sturm, (int64_t)S.redo_sturm);
 }
 
 // Resets the control block and the queue cells (no memset nodes, so that the
@@ -1983,6 +1997,12 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
     }
     const double bnorm = fmax(fabs(gl), fabs(gu));
     const double tol = kEps * sqrt((double)n) * bnorm;
+    // The tree works on 2^-k T with the Gershgorin bound in [1/2, 1): a
+    // power of two changes no rounding, keeps squares of the entries and the
+    // products of the division-free Sturm counts away from overflow and
+    // underflow, and is undone exactly on the eigenvalues.
+    const int kexp = (bnorm > 0.0 && __builtin_isfinite(bnorm)) ? __builtin_amdgcn_frexp_exp(bnorm) : 0;
+    const double tsc = __builtin_ldexp(1.0, -kexp);
     Block* B = P.blocks + pr->row0;
     int nb = 0;
     int64_t start = 0;
@@ -2024,8 +2044,8 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
             w0 = 1;
             w1 = nbk;
         } else if (pr->range == 1) {
-            const double sig = (l == 0) ? pr->vl : pr->vu;
-            const int c = negcount_T(S, P.d + B[b].row0, P.e + B[b].row0, nbk, sig);
+            const double sig = ((l == 0) ? pr->vl : pr->vu) * tsc;
+            const int c = negcount_T(S, P.d + B[b].row0, P.e + B[b].row0, nbk, tsc, sig);
             w0 = (int64_t)__shfl(c, 0) + 1;
             w1 = (int64_t)__shfl(c, 1);
         } else {
@@ -2047,6 +2067,8 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
         pr->m = err ? 0 : m;
         pr->nblocks = nb;
         pr->bnorm = bnorm;
+        pr->tscale = tsc;
+        pr->tscale_inv = __builtin_ldexp(1.0, kexp);
         pr->flags = (nb > 1) ? 1 : 0;
         __hip_atomic_fetch_add(&P.ctl->n_blocks, (int64_t)nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }

@@ -250,3 +250,42 @@ def test_split_blocks_with_interleaved_spectra(orc):
     top = np.abs(Z[:500]).max(axis=0) > 0
     bot = np.abs(Z[500:]).max(axis=0) > 0
     assert not np.any(top & bot)
+
+
+# ------------------------------------------- ranges of the division-free counts
+
+
+@pytest.mark.parametrize("k", [-900, -600, 600, 900])
+def test_power_of_two_scaling_is_exact(k):
+    """2^k T: the tree works on T scaled by a power of two into a Gershgorin
+    bound in [1/2, 1), so the eigenvalues are exactly 2^k times those of T
+    and the vectors are bit for bit the same, for scalings that would
+    overflow or underflow the squares of the entries."""
+    for d, e in (ti.random_uniform(300, 3), ti.glued_wilkinson(200)):
+        w, Z = gpu_solve(d, e)
+        ws, Zs = gpu_solve(np.ldexp(d, k), np.ldexp(e, k))
+        assert np.array_equal(ws, np.ldexp(w, k))
+        assert np.array_equal(Zs, Z)
+        wv = gpu_solve(np.ldexp(d, k), np.ldexp(e, k), eigvals_only=True)
+        assert np.array_equal(wv, np.ldexp(gpu_solve(d, e, eigvals_only=True), k))
+
+
+def test_sturm_counts_take_the_division_free_form():
+    """Entries of an ordinary size: no pass falls back to the guarded forms."""
+    import paper_1401_4950_amd as mr
+    d, e = ti.random_uniform(1000, 0)
+    gpu_solve(d, e)
+    assert mr.last_stats()["n_sturm_guarded"] == 0
+
+
+def test_tiny_diagonal_entries_use_the_guarded_count(orc):
+    """Diagonal entries of 2^-300 lie outside the range of the division-free
+    count on T (the root's bisection), which then counts in IEEE form."""
+    import paper_1401_4950_amd as mr
+    d, e = ti.random_uniform(400, 5)
+    d = d.copy()
+    d[::7] = np.ldexp(1.0, -300)
+    w, Z = gpu_solve(d, e)
+    assert mr.last_stats()["n_sturm_guarded"] > 0
+    wo, Zo = orc.solve(d, e)
+    check_pairs(d, e, w, Z, wo, Zo)
