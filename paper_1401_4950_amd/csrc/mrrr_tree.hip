@@ -211,7 +211,8 @@ DEV bool rep_commit(Shared& S, const RepRow& f) {
     S.tr[l] = x;
     __syncthreads();
     return (f.d == 0.0 && f.l == 0.0) ||
-           (fabs(x.d) >= 0x1p-150 && (f.l == 0.0 || fabs(x.dll) >= 0x1p-150));
+           (fabs(x.d) >= 0x1p-150 && fabs(x.d) <= 0x1p150 &&
+            (f.l == 0.0 || (fabs(x.dll) >= 0x1p-150 && fabs(x.dll) <= 0x1p150)));
 }
 
 // Rows of T (row i couples to row i-1), multiplied by the problem's
@@ -240,7 +241,8 @@ DEV bool T_commit(Shared& S, const RepRow& f) {
     x.pad = 0.0;
     S.tr[l] = x;
     __syncthreads();
-    return (f.d == 0.0 || fabs(f.d) >= 0x1p-150) && (f.l == 0.0 || fabs(x.dll) >= 0x1p-150);
+    return (f.d == 0.0 || (fabs(f.d) >= 0x1p-150 && fabs(f.d) <= 0x1p150)) &&
+           (f.l == 0.0 || (fabs(x.dll) >= 0x1p-150 && fabs(x.dll) <= 0x1p150));
 }
 
 // ------------------------------------------------------------ Sturm counts
@@ -274,19 +276,35 @@ DEV int negcount_rep_guarded(Shared& S, const double* D, const double* L, int64_
 // is no quotient), so the count is that of the same nearby representation the
 // error analysis of the stationary transform allows.  The pair (u, v) is
 // scaled by a power of two every 8 rows, which changes no sign and no
-// rounding.  The relative-error argument needs every rounded result to be
-// normal or an exact zero; it holds when the data and sigma are at least
-// kHomData in magnitude (or zero) and every u, w met is at least kHomState
-// (then every exact result is a multiple of 2^-1074, so a zero is exact and a
-// nonzero result is caught by the check if it is tiny).  A lane outside these
-// bounds, or with a non-finite (u, v) at the end, counts again with the
-// guarded quotient form.  One row costs two dependent fused multiply-adds
-// instead of a reciprocal and four corrections; the sign bits of 32 rows are
-// shifted into one word and counted with one popcount.
+// rounding.
+//
+// The relative-error argument needs every rounded result to carry a relative
+// error of one rounding (or an absolute one far below it).  It holds when the
+// data d_i, d_i l_i^2 and sigma lie in [2^-150, 2^150] (or are zero) and every
+// w met, and every v after a rescaling, is at least kHomState = 2^-800:
+//   * d_i v_i and u_i lie on the 2^-1074 grid (ulp(d) ulp(v) >= 2^-1054), so
+//     their sum w_i is exact when subnormal and zero only when exactly zero;
+//     a tiny w fails the check;
+//   * |sigma w_i| >= 2^-950, so u_{i+1} is a normal result, or an exact one
+//     after a cancellation (then u_i l l d is normal and on the grid), and the
+//     at most 2^-1075 that a subnormal product u_i (d l^2) or a rescaled tiny u
+//     can be off is below 2^-120 of |u_{i+1}| (|d l^2| <= 2^150).
+// A lane outside these bounds, or with a non-finite (u, v) at the end (an
+// overflow persists as inf or NaN), counts again with the guarded quotient
+// form.  One row costs two dependent fused multiply-adds instead of a
+// reciprocal and four corrections; the sign bits of 32 rows are shifted into
+// one word and counted with one popcount.
 constexpr double kHomData = 0x1p-150;
 constexpr double kHomState = 0x1p-800;
+// s_waitcnt lgkmcnt(8) (vmcnt and expcnt left at their maxima): the LDS reads
+// of the group before the last 8 are complete
+constexpr int kWaitLds8 = 0xC87F;
 
 DEV unsigned hi32(double x) { return (unsigned)((unsigned long long)__double_as_longlong(x) >> 32); }
+
+DEV bool hom_sigma_ok(double sigma) {
+    return sigma == 0.0 || (fabs(sigma) >= kHomData && fabs(sigma) <= 0x1p150);
+}
 
 DEV void hom_rescale(double& u, double& v, double& mw) {
     const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(u), fabs(v)));
@@ -297,7 +315,7 @@ DEV void hom_rescale(double& u, double& v, double& mw) {
 
 DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, double sigma) {
     double u = -sigma, v = 1.0;
-    double mw = 1.0, mu = 1.0;   // smallest |w| and |u| met
+    double mw = 1.0;             // smallest |w| met (and |v| after rescaling)
     unsigned B = 0, Bold = 0;    // sign bits of the last rows, newest in bit 0
     int cnt = 0;
     bool data_ok = true;
@@ -316,14 +334,15 @@ DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, dou
 #pragma unroll
                     for (int k = 0; k < 8; ++k) nxt[k] = QROW_DDLL(S, (g + 1) * 8 + k);
                 }
-                // keep the next group's LDS reads ahead of this group's rows
+                // the next group's LDS reads stay ahead of this group's rows,
+                // and one wait covers the 8 rows of this group
                 __builtin_amdgcn_sched_barrier(0);
+                if (g + 1 < kTile / 8) __builtin_amdgcn_s_waitcnt(kWaitLds8);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const double w = __builtin_fma(cur[k].x, v, u);
                     const double p = u * cur[k].y;
                     B = __builtin_amdgcn_alignbit(B, hi32(w), 31);
-                    mu = fmin(mu, fabs(u));
                     u = __builtin_fma(-sigma, w, p);
                     v = w;
                     mw = fmin(mw, fabs(w));
@@ -344,7 +363,6 @@ DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, dou
                 const double w = __builtin_fma(x.x, v, u);
                 cnt += sbit(w) ^ sbit(v);
                 const double p = u * x.y;
-                mu = fmin(mu, fabs(u));
                 u = __builtin_fma(-sigma, w, p);
                 v = w;
                 mw = fmin(mw, fabs(w));
@@ -352,10 +370,8 @@ DEV int negcount_rep(Shared& S, const double* D, const double* L, int64_t n, dou
             }
         }
     }
-    // sigma = 0 keeps u = 0 exactly (then w_i = d_i v_i); otherwise a zero u
-    // is an exact zero too but is sent to the guarded form with the tiny ones
-    const bool sig_ok = sigma == 0.0 || fabs(sigma) >= kHomData;
-    const bool bad = !data_ok || !sig_ok || !(mw >= kHomState) || (sigma != 0.0 && !(mu >= kHomState)) ||
+    // sigma = 0 keeps u = 0 exactly (then w_i = d_i v_i)
+    const bool bad = !data_ok || !hom_sigma_ok(sigma) || !(mw >= kHomState) ||
                      !__builtin_isfinite(u) || !__builtin_isfinite(v);
     if (wave_or(bad ? 1 : 0)) {
         const int c2 = negcount_rep_guarded(S, D, L, n, sigma);
@@ -418,6 +434,7 @@ DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, doubl
                     for (int k = 0; k < 8; ++k) nxt[k] = QROW_DDLL(S, (g + 1) * 8 + k);
                 }
                 __builtin_amdgcn_sched_barrier(0);
+                if (g + 1 < kTile / 8) __builtin_amdgcn_s_waitcnt(kWaitLds8);
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const double c = cur[k].x - sigma;
@@ -432,7 +449,8 @@ DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, doubl
                     cnt += __builtin_popcount(B ^ __builtin_amdgcn_alignbit(Bold, B, 1));
                     Bold = B;
                 }
-                hom_rescale(a, b, mw);
+                hom_rescale(b, a, mw);
+                mw = fmin(mw, fabs(b));
 #pragma unroll
                 for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
             }
@@ -444,12 +462,13 @@ DEV int negcount_T(Shared& S, const double* d, const double* e, int64_t n, doubl
                 b = a;
                 a = pn;
                 mw = fmin(mw, fabs(pn));
-                hom_rescale(a, b, mw);
+                hom_rescale(b, a, mw);
+                mw = fmin(mw, fabs(b));
             }
         }
     }
-    const bool sig_ok = sigma == 0.0 || fabs(sigma) >= kHomData;
-    const bool bad = !data_ok || !sig_ok || !(mw >= kHomState) || !__builtin_isfinite(a) || !__builtin_isfinite(b);
+    const bool bad = !data_ok || !hom_sigma_ok(sigma) || !(mw >= kHomState) || !__builtin_isfinite(a) ||
+                     !__builtin_isfinite(b);
     if (wave_or(bad ? 1 : 0)) {
         const int c2 = negcount_T_ieee(S, d, e, n, sc, sigma);
         if (bad) cnt = c2;
