@@ -12,7 +12,9 @@
 //   negcount_rep   NegCount on L D L^T (App. B, Alg. B.2): the sign count of
 //                  the stationary qd transform.
 //   negcount_T     NegCount on T (App. B, Alg. B.1), for the root.
-//   dstqds         L+ D+ L+^T = L D L^T - tau I (Alg. 3.5), for new RRRs.
+//   dstqds_select  the stationary transform (Alg. 3.5) for the candidate shifts
+//   dstqds_values  of Alg. 3.8, one per lane, and the winner's rows, 64-row
+//                  tiles in parallel from the selection's checkpoints.
 //   twisted        dstqds + the progressive transform (Alg. 3.6) + gamma_k
 //                  and the twist index r = argmin |gamma_k| (Alg. 3.7), with
 //                  the norm of the solution of N_r^T z = e_r accumulated as
@@ -1143,33 +1145,33 @@ struct FacOut {
 };
 
 // L+ D+ L+^T = L D L^T - tau I by the differential stationary qd transform
-// (Alg. 3.5), one shift per lane, written to (Dp, Lp) by the `act` lanes.
-// ok = the factorisation exists (all pivots finite and nonzero); growth =
-// ||D+||_max.  Quotients come from the reciprocal with no per-row test: a
-// zero or infinite pivot makes the IEEE form fail `ok`, and turns the
-// reciprocal form into NaN, which fails it too, so both forms accept the
-// same candidates and a failed candidate is never used.  Rows are read from
-// LDS in groups of kAhead, one group ahead of the arithmetic.
-DEV FacOut dstqds(Shared& S, const double* D, const double* L, int64_t n, double tau, bool act,
-                  double* Dp, double* Lp) {
+// (Alg. 3.5), in two passes.  dstqds_select: the shift selection of Alg. 3.8
+// without writing any candidate -- one candidate shift tau per lane runs the
+// transform (quotients from the reciprocal, see quot), recording whether the
+// factorisation exists (every d+ and l+ finite, every d+ nonzero; a zero or
+// infinite pivot turns the reciprocal form into NaN, which fails the test as
+// well) and its element growth max |d+_i|, and keeping the state s entering
+// every 64-row tile ([tile][lane]) so that dstqds_values can recompute the
+// winner's rows tile by tile in parallel, bit for bit as one sequential pass
+// computes them.
+DEV FacOut dstqds_select(Shared& S, const double* D, const double* L, int64_t n, double tau, double* cks) {
+    const int l = lane_id();
     double s = -tau, gmax = 0.0;
     int ok = 1;
-    auto row = [&](int64_t i, const QRow& x) {
+    auto row = [&](const QRow& x) {
         const double dp = s + x.d;
-        if (act) Dp[i] = dp;
         ok &= (__builtin_isfinite(dp) && dp != 0.0) ? 1 : 0;
         gmax = fmax(gmax, fabs(dp));
-        // the last row has dl = dll = 0 (rep_fetch): lp = 0 there, and
-        // Lp[n-1] lies inside the 2n-double block of the representation
         const Recip rc = recip(dp);
         const double lp = quot(rc, x.dl);
-        if (act) Lp[i] = lp;
         ok &= __builtin_isfinite(lp) ? 1 : 0;
         s = quot(rc, s) * x.dll - tau;
     };
     RepRow f = rep_fetch(D, L, 0, n);
-    for (int64_t base = 0; base < n; base += kTile) {
+    int64_t tile = 0;
+    for (int64_t base = 0; base < n; base += kTile, ++tile) {
         rep_commit(S, f);
+        cks[tile * kWave + l] = s;
         if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         if (lim == kTile) {
@@ -1183,18 +1185,56 @@ DEV FacOut dstqds(Shared& S, const double* D, const double* L, int64_t n, double
                     for (int u = 0; u < kAhead; ++u) nxt[u] = S.tr[(g + 1) * kAhead + u];
                 }
 #pragma unroll
-                for (int u = 0; u < kAhead; ++u) row(base + g * kAhead + u, cur[u]);
+                for (int u = 0; u < kAhead; ++u) row(cur[u]);
 #pragma unroll
                 for (int u = 0; u < kAhead; ++u) cur[u] = nxt[u];
             }
         } else {
-            for (int t = 0; t < lim; ++t) row(base + t, S.tr[t]);
+            for (int t = 0; t < lim; ++t) row(S.tr[t]);
         }
     }
     FacOut o;
     o.ok = ok;
     o.growth = gmax;
     return o;
+}
+
+// The rows of the candidate that lane c ran in dstqds_select, written to
+// (Dp, Lp): the 64-row tiles go round the lanes, each lane restarting the
+// transform from the s its tile was entered with, in the arithmetic of
+// dstqds, so the result is bit for bit that of one sequential pass.  Rows are
+// read eight ahead of the recurrence.
+DEV void dstqds_values(const double* D, const double* L, int64_t n, double tau, const double* cks, int c,
+                       double* Dp, double* Lp) {
+    const int l = lane_id();
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    for (int64_t tile = l; tile < ntiles; tile += kWave) {
+        double s = cks[tile * kWave + c];
+        const int64_t base = tile * kTile;
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        for (int t0 = 0; t0 < lim; t0 += 8) {
+            double dd[8], ll[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t i = base + t0 + k;
+                dd[k] = (t0 + k < lim) ? D[i] : 0.0;
+                ll[k] = (t0 + k < lim && i < n - 1) ? L[i] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (t0 + k < lim) {
+                    const int64_t i = base + t0 + k;
+                    const double dl = dd[k] * ll[k];
+                    const double dll = dl * ll[k];
+                    const double dp = s + dd[k];
+                    Dp[i] = dp;
+                    const Recip rc = recip(dp);
+                    Lp[i] = quot(rc, dl);
+                    s = quot(rc, s) * dll - tau;
+                }
+            }
+        }
+    }
 }
 
 // T - mu I = L D L^T by Gaussian elimination without pivoting; sgn > 0
@@ -1611,19 +1651,20 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     const double rgap = ld_rlx_d(P.gap + sb + q);
     // 2. shifts just outside both ends; keep the candidate with the smaller
     //    element growth; back off while the growth is too large (Alg. 3.8)
-    const int64_t off = arena_alloc(P, 4 * n);
+    // the new representation's D+ and L+, then the selection's checkpoints
+    const int64_t off = arena_alloc(P, 4 * n + 128);
     if (off < 0) return;
-    double* C0 = P.arena + off;
-    double* C1 = P.arena + off + 2 * n;
-    // All back-off levels of Alg. 3.8 are factorised at once: lane 2t uses
+    double* Cn = P.arena + off;
+    double* cks = Cn + 2 * n;
+    // All back-off levels of Alg. 3.8 are tried at once: lane 2t uses
     // tau_l(t) and lane 2t+1 tau_r(t).  Level 0 sits 100 eps |lambda|
     // outside the cluster; levels 1..T-1 back off geometrically from
-    // 100 eps |lambda| + eps spdiam up to a quarter of the gap to the nearest
-    // eigenvalue outside the cluster on that side, so that no level moves the
-    // shift past the cluster's neighbours (which would keep the cluster from
-    // being broken).  The selection below is the algorithm's sequential rule:
-    // the first level whose better candidate passes the growth test wins;
-    // otherwise the least growth seen.  Only level 0 stores its pair.
+    // 100 eps |lambda| up to a quarter of the gap to the nearest eigenvalue
+    // outside the cluster on that side, so that no level moves the shift past
+    // the cluster's neighbours (which would keep the cluster from being
+    // broken).  The selection below is the algorithm's sequential rule: the
+    // first level whose better candidate passes the growth test wins;
+    // otherwise the least growth seen.  Only the winner's rows are written.
     const double spd = par.spdiam;
     const double thresh = 8.0 * spd;    // ||D+|| = O(spdiam): accept at once
     const int T = P.max_tries < 32 ? P.max_tries : 32;
@@ -1650,10 +1691,10 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         const double del = dmin * pow(dmax / dmin, frac);
         mytau = side ? tau_r0 + del : tau_l0 - del;
     }
-    const FacOut f = dstqds(S, D, L, n, mytau, tt == 0, side ? C1 : C0, (side ? C1 : C0) + n);
+    const FacOut f = dstqds_select(S, D, L, n, mytau, cks);
     steps += 2 * n * T;
     double best = __builtin_inf(), best_tau = 0.0;
-    int chosen = -1;
+    int chosen = -1, best_lane = 0;
     double tau = 0.0, chosen_growth = 0.0;
     for (int t = 0; t < T; ++t) {
         const int ok0 = __shfl(f.ok, 2 * t), ok1 = __shfl(f.ok, 2 * t + 1);
@@ -1666,9 +1707,9 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         if (pick < 0) continue;
         const double g = pick ? g1 : g0;
         const double tp = pick ? t1 : t0;
-        if (g < best) { best = g; best_tau = tp; }
+        if (g < best) { best = g; best_tau = tp; best_lane = 2 * t + pick; }
         if (g <= thresh && chosen < 0) {
-            chosen = (t == 0) ? pick : 2;   // 2: not stored yet
+            chosen = 2 * t + pick;
             tau = tp;
             chosen_growth = g;
         }
@@ -1680,21 +1721,20 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
             return;
         }
         // no candidate passed: the least element growth (Alg. 3.8, last line)
-        chosen = 2;
+        chosen = best_lane;
         tau = best_tau;
         chosen_growth = best;
         unverified = 1;
     }
-    if (chosen == 2) {
-        dstqds(S, D, L, n, tau, l == 0, C0, C0 + n);
-        steps += n;
-        chosen = 0;
-    }
+    // the checkpoints of lane `chosen` go to every lane
+    __syncthreads();
+    dstqds_values(D, L, n, tau, cks, chosen, Cn, Cn + n);
+    steps += n;
     const int id = new_node(P);
     if (id < 0) return;
     if (l == 0) {
         Node nd;
-        nd.data = off + (chosen ? 2 * n : 0);
+        nd.data = off;
         nd.block = par.block;
         nd.depth = par.depth + 1;
         nd.a = p;
