@@ -1037,39 +1037,35 @@ DEV int try_pop(const Params& P, int q, Task* out) {   // one lane
 // with everything this wave wrote before (a release writes back the XCD's L2,
 // so it is paid once per push, not once per cell); the sequence numbers then
 // go out as relaxed stores.
-template <class Gen>
-DEV bool push_batch(const Params& P, int q, int count, Gen gen) {
-    if (count <= 0) return true;
-    const int l = lane_id();
+DEV uint64_t push_reserve(const Params& P, int q, int count) {
     uint64_t first = 0;
-    if (l == 0) {
+    if (lane_id() == 0) {
         __hip_atomic_fetch_add(&P.ctl->pending, (int64_t)count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         first = __hip_atomic_fetch_add(P.ctl->tail(q), (uint64_t)count, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     }
-    first = __shfl(first, 0);
-    const uint64_t cap = P.qcap[q];
-    bool ok = true;
-    for (int k = l; k < count; k += kWave) {
-        const uint64_t pos = first + (uint64_t)k;
-        const uint64_t cell = pos % cap;
-        // wait until the cell is free for this ticket (bounded)
-        int spin = 0;
-        while (__hip_atomic_load(&P.seq[q][cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos) {
-            if (++spin > (1 << 22) || __hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                ok = false;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (!ok) break;
-        P.q[q][cell] = gen(k);
+    return __shfl(first, 0);
+}
+
+// Waits (bounded) until the cell of ticket `pos` is free, then writes it.
+DEV bool push_fill(const Params& P, int q, uint64_t pos, const Task& t) {
+    const uint64_t cell = pos % P.qcap[q];
+    int spin = 0;
+    while (__hip_atomic_load(&P.seq[q][cell], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos) {
+        if (++spin > (1 << 22) || __hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return false;
+        __builtin_amdgcn_s_sleep(1);
     }
+    P.q[q][cell] = t;
+    return true;
+}
+
+DEV bool push_publish(const Params& P, int q, uint64_t first, int count, bool ok) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (ok) {
-        for (int k = l; k < count; k += kWave) {
+        for (int k = lane_id(); k < count; k += kWave) {
             const uint64_t pos = first + (uint64_t)k;
-            __hip_atomic_store(&P.seq[q][pos % cap], pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&P.seq[q][pos % P.qcap[q]], pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     if (__ballot(!ok) != 0ull) {
@@ -1079,33 +1075,132 @@ DEV bool push_batch(const Params& P, int q, int count, Gen gen) {
     return true;
 }
 
+template <class Gen>
+DEV bool push_batch(const Params& P, int q, int count, Gen gen) {
+    if (count <= 0) return true;
+    const uint64_t first = push_reserve(P, q, count);
+    bool ok = true;
+    for (int k = lane_id(); k < count && ok; k += kWave) ok = push_fill(P, q, first + (uint64_t)k, gen(k));
+    return push_publish(P, q, first, count, ok);
+}
+
 DEV bool push_one(const Params& P, int q, Task t) {
     return push_batch(P, q, 1, [&](int) { return t; });
 }
 
-// Refinement slices of members [a, b] of a node (R-tasks of Sec. 4.1.3): the
-// slice size follows the thesis' rule of thumb -- about twice as many slices
-// as workers -- clamped to [slice_min, slice_max] eigenvalues.  With many
-// matrices in one launch a block gets the share of the workers that its rows
-// are of all rows, so that small blocks are not cut into one-member slices.
-DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64_t block_rows, int smax) {
-    const int64_t M = (int64_t)b - a + 1;
+// Refinement slices of members [a, b] of a node (R-tasks of Sec. 4.1.3),
+// sized by the work each member still needs.  A member whose bracket must
+// shrink by 2^bits to reach the accuracy of `mode` needs bits / log2(L + 1)
+// multisection passes with L points; a slice of s members gives each
+// L = 64 / s points (at most `lanes`).  For a pass budget Pb every member has
+// a capacity -- the largest power-of-two slice that still finishes it in Pb
+// passes -- and each 64-member chunk is cut into the largest aligned
+// power-of-two blocks whose members all fit.  Pb starts at what the hardest
+// member needs alone and grows until the slices number at most the node's
+// share of the workers (the workers times the share of all rows that the
+// block has), so that one round of slices finishes the node: the
+// refinement's critical path is the hardest member's passes, not a fixed
+// slice size's.  Slices are at least slice_min (a power of two) and at most
+// smax members.
+DEV int member_bits(const Params& P, int mode, double lo, double hi) {
+    const double w = hi - lo;
+    const double mx = fmax(fabs(lo), fabs(hi));
+    const double tgt = (mode == kModeFull) ? fmax(2.0 * kEps * mx, 2.0 * kSafmin) : fmax(P.rtol * mx, 2.0 * kSafmin);
+    if (!(w > tgt)) return 0;
+    const double ratio = w / tgt;
+    return __builtin_isfinite(ratio) ? __builtin_amdgcn_frexp_exp(ratio) : 1100;
+}
+
+DEV double slice_bpp(int s, int lanes) {   // bits per pass of an s-member slice
+    int lg = kWave / s;
+    if (lg > lanes) lg = lanes;
+    return log2((double)lg + 1.0);
+}
+
+// The cut of the 64-member chunk starting at member `base`: whether this
+// lane's member starts a slice, and the slice's size.
+DEV void slice_cut(const Params& P, int64_t sb, int b, int mode, int Pb, int qmin, int qmax, int lanes, int base,
+                   bool* start, int* size) {
+    const int l = lane_id();
+    const int j = base + l;
+    int cap = kWave;
+    if (j <= b) {
+        const int bits = member_bits(P, mode, ld_rlx_d(P.lo + sb + j), ld_rlx_d(P.hi + sb + j));
+        cap = 1;
+        for (int sz = kWave; sz >= 2; sz >>= 1) {
+            if ((double)Pb * slice_bpp(sz, lanes) >= (double)bits) {
+                cap = sz;
+                break;
+            }
+        }
+    }
+    // mins[q] = least capacity in the aligned block of 2^q members
+    int mins[7];
+    int m = cap;
+    mins[0] = m;
+    for (int q = 0; q < 6; ++q) {
+        m = min(m, __shfl_xor(m, 1 << q));
+        mins[q + 1] = m;
+    }
+    int q = qmax;
+    while (q > qmin && mins[q] < (1 << q)) --q;
+    *size = 1 << q;
+    *start = (j <= b) && ((l & ((1 << q) - 1)) == 0);
+}
+
+DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64_t block_rows, int smax, int64_t sb,
+                     int lanes) {
+    const int l = lane_id();
     const double share = (double)P.nworkers * (double)block_rows / (double)(P.total_rows > 0 ? P.total_rows : 1);
-    int64_t sz = (int64_t)ceil((double)M / (2.0 * fmax(share, 0.5)));
-    if (sz > smax) sz = smax;
-    if (sz < P.slice_min) sz = P.slice_min;
-    const int ns = (int)((M + sz - 1) / sz);
-    if (lane_id() == 0)
-        __hip_atomic_store(&P.nodes[node_id].pending, ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    push_batch(P, kQRefine, ns, [&](int k) {
-        Task t;
-        t.type = kTaskRefine;
-        t.node = node_id;
-        t.a = a + (int)(k * sz);
-        const int64_t e = (int64_t)t.a + sz - 1;
-        t.b = (int)(e < b ? e : b) | (mode << 30);
-        return t;
-    });
+    const int budget = share < 1.0 ? 1 : (int)share;
+    int qmin = 0, qmax = 0;
+    while ((1 << (qmin + 1)) <= P.slice_min && qmin < 6) ++qmin;
+    while ((1 << (qmax + 1)) <= smax && qmax < 6) ++qmax;
+    if (qmax < qmin) qmax = qmin;
+    // the hardest member alone sets the least pass budget
+    int maxbits = 0;
+    for (int base = a; base <= b; base += kWave) {
+        const int j = base + l;
+        if (j <= b) maxbits = max(maxbits, member_bits(P, mode, ld_rlx_d(P.lo + sb + j), ld_rlx_d(P.hi + sb + j)));
+    }
+    for (int o = 32; o > 0; o >>= 1) maxbits = max(maxbits, __shfl_xor(maxbits, o));
+    const double best_bpp = slice_bpp(1 << qmin, lanes);
+    int Pb = (int)ceil((double)maxbits / best_bpp);
+    if (Pb < 1) Pb = 1;
+    int ns = 0;
+    for (int tries = 0; tries < 24; ++tries) {
+        ns = 0;
+        for (int base = a; base <= b; base += kWave) {
+            bool st;
+            int sz;
+            slice_cut(P, sb, b, mode, Pb, qmin, qmax, lanes, base, &st, &sz);
+            ns += __popcll(__ballot(st));
+        }
+        if (ns <= budget) break;
+        Pb += 1 + Pb / 4;
+    }
+    if (l == 0) __hip_atomic_store(&P.nodes[node_id].pending, ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t first = push_reserve(P, kQRefine, ns);
+    bool ok = true;
+    int done = 0;
+    for (int base = a; base <= b; base += kWave) {
+        bool st;
+        int sz;
+        slice_cut(P, sb, b, mode, Pb, qmin, qmax, lanes, base, &st, &sz);
+        const uint64_t sm = __ballot(st);
+        if (st && ok) {
+            Task t;
+            t.type = kTaskRefine;
+            t.node = node_id;
+            t.a = base + l;
+            const int e = t.a + sz - 1;
+            t.b = (e < b ? e : b) | (mode << 30);
+            const int k = done + __popcll(sm & ((1ull << l) - 1ull));
+            ok = (k < ns) && push_fill(P, kQRefine, first + (uint64_t)k, t);
+        }
+        done += __popcll(sm);
+    }
+    push_publish(P, kQRefine, first, ns, ok);
 }
 
 DEV int new_node(const Params& P) {   // all lanes get the id
@@ -1538,11 +1633,32 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         P.blocks[bid].root = id;
     }
     const int64_t sb = blk.row0 - 1;
+    // one multisection pass over the root bracket (64 points) places every
+    // member between two counted points, so that the refinement slices can
+    // be sized by the work each member still needs
+    {
+        const double sig = rlo + (rhi - rlo) * (double)(l + 1) / (double)(kWave + 1);
+        const int c = negcount_rep(S, Dr, Lr, n, sig);
+        steps += n * kWave;
+        __syncthreads();
+        S.m_cnt[l] = c;
+        S.m_sig[l] = sig;
+        __syncthreads();
+    }
     for (int64_t j = blk.k0 + l; j <= blk.k1; j += kWave) {
-        P.lo[sb + j] = rlo;
-        P.hi[sb + j] = rhi;
-        P.lo0[sb + j] = rlo;
-        P.hi0[sb + j] = rhi;
+        int a = 0, b = kWave;   // first point whose count reaches j
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (S.m_cnt[mid] >= j) b = mid; else a = mid + 1;
+        }
+        double lo = rlo, hi = rhi;
+        // only points whose own count confirms them become bracket ends
+        if (a < kWave && S.m_cnt[a] >= j) hi = S.m_sig[a];
+        if (a > 0 && S.m_cnt[a - 1] < j) lo = S.m_sig[a - 1];
+        P.lo[sb + j] = lo;
+        P.hi[sb + j] = hi;
+        P.lo0[sb + j] = lo;
+        P.hi0[sb + j] = hi;
         P.vflag[sb + j] = 3;
     }
     if (l == 0) {
@@ -1552,7 +1668,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     }
     add_stat(&P.ctl->n_nodes, 1);
     push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, blk.n,
-                P.probs[blk.prob].slice_max);
+                P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes);
 }
 
 DEV void load_members(Shared& S, const Params& P, int64_t sb, int a, int M) {
@@ -1782,7 +1898,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (l == 0) {
         __hip_atomic_fetch_max(&P.ctl->dmax, par.depth + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    push_slices(P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max);
+    push_slices(P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes);
 }
 
 // A bundle of singletons of one node, one per lane (Alg. 4.3): Rayleigh
