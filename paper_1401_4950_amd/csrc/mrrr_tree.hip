@@ -519,6 +519,63 @@ DEV bool bracket_done(const Params& P, int mode, double lo, double hi) {
     return w <= fmax(P.rtol * mx, 2.0 * kSafmin);       // Alg. 3.3 stopping rule
 }
 
+// The t-th of L multisection points inside (lo, hi), increasing in t.
+// Equally spaced, except where the bracket reaches (to within 2^-8 of its
+// extent) to zero, where an eigenvalue of the representation may be tiny
+// (an eigenvalue next to the root's or a cluster's shift): then half of the
+// points are spaced geometrically toward zero, down to 2^-120 of the first
+// equally spaced point (and not below 2^-140), so that one pass finds the
+// eigenvalue's binade.
+// (no geometric point below 2^-140: the division-free count sends shifts
+// below 2^-150 to the guarded form; an eigenvalue that small is still found,
+// by equally spaced points)
+constexpr double kGeoFloor = 0x1p-140;
+DEV double geo_point(double a, double x1, int k, int h) {   // k-th of h in (a, x1)
+    const double fr = (double)(k + 1) / (double)(h + 1);
+    if (!(a >= kGeoFloor && x1 > a)) return x1 * fr;   // too close to zero: equally spaced
+    return a * exp2(log2(x1 / a) * fr);
+}
+DEV double msec_point_pos(double lo, double hi, int t, int L) {   // 0 <= lo < hi
+    const int h = L / 2, nl = L - h;
+    const double w = hi - lo;
+    const double x1 = lo + w / (double)(nl + 1);
+    if (t >= h) return lo + w * (double)(t - h + 1) / (double)(nl + 1);
+    const double a = fmax(lo, fmax(x1 * 0x1p-120, kGeoFloor));
+    return geo_point(a, x1, t, h);
+}
+DEV double msec_point(double lo, double hi, int t, int L) {
+    const double w = hi - lo;
+    if (L >= 4 && w > 0.0) {
+        if (lo >= 0.0 && lo < hi * 0x1p-8) return msec_point_pos(lo, hi, t, L);
+        if (hi <= 0.0 && -hi < -lo * 0x1p-8) return -msec_point_pos(-hi, -lo, L - 1 - t, L);
+        if (lo < 0.0 && hi > 0.0) {
+            // equally spaced points, and in the gap that holds zero, zero
+            // and geometric points toward it on both sides
+            const int nl = L / 2, hg = (L - nl - 1) / 2, hp = L - nl - 1 - hg;
+            const int k0 = (int)((-lo / w) * (double)(nl + 1));   // equally spaced points below zero
+            const int kb = k0 < nl ? k0 : nl;
+            if (t < kb) return lo + w * (double)(t + 1) / (double)(nl + 1);
+            int u = t - kb;
+            const double xl = lo + w * (double)kb / (double)(nl + 1);       // last point below zero (or lo)
+            const double xr = lo + w * (double)(kb + 1) / (double)(nl + 1); // first point above zero (or hi)
+            if (u < hg) {
+                const double m = -fmin(xl, 0.0);
+                return -geo_point(fmax(m * 0x1p-120, kGeoFloor), m, hg - 1 - u, hg);
+            }
+            u -= hg;
+            if (u == 0) return 0.0;
+            u -= 1;
+            if (u < hp) {
+                const double m = fmax(xr, 0.0);
+                return geo_point(fmax(m * 0x1p-120, kGeoFloor), m, u, hp);
+            }
+            u -= hp;
+            return lo + w * (double)(kb + 1 + u) / (double)(nl + 1);
+        }
+    }
+    return lo + w * (double)(t + 1) / (double)(L + 1);
+}
+
 DEV void refine_members(Shared& S, const Params& P, const double* D, const double* L, int64_t n,
                         int M, const MemberCtx& C, int64_t& steps) {
     const int l = lane_id();
@@ -532,7 +589,7 @@ DEV void refine_members(Shared& S, const Params& P, const double* D, const doubl
     }
     if (joint) {
         const double lo = S.m_lo[0], hi = S.m_hi[0];
-        const double sig = lo + (hi - lo) * (double)(l + 1) / (double)(kWave + 1);
+        const double sig = msec_point(lo, hi, l, kWave);
         const int c = negcount_rep(S, D, L, n, sig);
         steps += (int64_t)n * kWave;
         __syncthreads();
@@ -602,7 +659,7 @@ DEV void refine_members(Shared& S, const Params& P, const double* D, const doubl
             else role = vlo ? 1 : 2;
             sig = (role == 1) ? lo : hi;
         } else {
-            sig = lo + w * (double)(t + 1) / (double)(Lg + 1);
+            sig = msec_point(lo, hi, t, Lg);
         }
         if (!valid) sig = 0.0;
         const int c = negcount_rep(S, D, L, n, sig);
@@ -1108,7 +1165,12 @@ DEV int member_bits(const Params& P, int mode, double lo, double hi) {
     const double tgt = (mode == kModeFull) ? fmax(2.0 * kEps * mx, 2.0 * kSafmin) : fmax(P.rtol * mx, 2.0 * kSafmin);
     if (!(w > tgt)) return 0;
     const double ratio = w / tgt;
-    return __builtin_isfinite(ratio) ? __builtin_amdgcn_frexp_exp(ratio) : 1100;
+    int bits = __builtin_isfinite(ratio) ? __builtin_amdgcn_frexp_exp(ratio) : 1100;
+    // a bracket that reaches zero may hold a tiny eigenvalue: the binade
+    // search costs about two more passes
+    const bool reach = (lo <= 0.0 && hi >= 0.0) || (lo > 0.0 && lo < hi * 0x1p-8) || (hi < 0.0 && hi > lo * 0x1p-8);
+    if (reach) bits += 12;
+    return bits;
 }
 
 DEV double slice_bpp(int s, int lanes) {   // bits per pass of an s-member slice
@@ -1637,7 +1699,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     // member between two counted points, so that the refinement slices can
     // be sized by the work each member still needs
     {
-        const double sig = rlo + (rhi - rlo) * (double)(l + 1) / (double)(kWave + 1);
+        const double sig = msec_point(rlo, rhi, l, kWave);
         const int c = negcount_rep(S, Dr, Lr, n, sig);
         steps += n * kWave;
         __syncthreads();
