@@ -790,12 +790,17 @@ DEV TwistOut twisted_impl(Shared& S, const double* D, const double* L, int64_t n
     if (live) ck.at(cl, 2) = p;
     const int64_t last_tile = ((n - 1) / kTile) * kTile;
     RepRow fb_ = rep_fetch(D, L, last_tile, n);
+    // the forward checkpoint of the block after the current one is loaded a
+    // block ahead, so that its latency hides behind the current block
+    double s_next = live ? ck.at(cl, 0) : 0.0;
     for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
         rep_commit(S, fb_);
         if (tb - kTile >= 0) fb_ = rep_fetch(D, L, tb - kTile, n);
         const int64_t cfirst = tb / kCkb;
         const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
         for (int64_t c = clast; c >= cfirst; --c) {
+            const double s_blk = s_next;
+            s_next = (live && c >= 1) ? ck.at(c - 1, 0) : 0.0;
             const int64_t b0 = c * kCkb;
             const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);   // rows [b0, b1)
             if (b0 >= b1) continue;
@@ -808,7 +813,7 @@ DEV TwistOut twisted_impl(Shared& S, const double* D, const double* L, int64_t n
                 const int k = (int)(b0 + t - tb);
                 xr[t] = S.tr[k < kTile ? k : kTile - 1];
             }
-            double sr = live ? ck.at(c, 0) : 0.0;
+            double sr = s_blk;
 #pragma unroll
             for (int t = 0; t < kCkb; ++t) {
                 sreg[t] = sr;
@@ -900,6 +905,8 @@ DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_
     if (live && write) zcol[r] = scale;
     // ---- upward: rows r+1 .. n-1
     double zc = 1.0, zm1 = 0.0, zr1 = 0.0;   // z_i, z_{i-1}, saved z_{r+1}
+    const int64_t cl = (n - 1) / kCkb;
+    double p_next = live ? ck.at(0, 2) : 0.0;   // checkpoints loaded a block ahead
     RepRow fu = rep_fetch(D, L, 0, n);
     for (int64_t tb = 0; tb < n; tb += kTile) {
         rep_commit(S, fu);
@@ -907,6 +914,8 @@ DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_
         const int64_t cfirst = tb / kCkb;
         const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
         for (int64_t c = cfirst; c <= clast; ++c) {
+            const double p_blk = p_next;
+            p_next = (live && c + 1 <= cl) ? ck.at(c + 1, 2) : 0.0;
             const int64_t b0 = c * kCkb;
             const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
             if (b0 >= b1) continue;
@@ -917,7 +926,7 @@ DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_
                 const int k = (int)(b0 + t - tb);
                 xr[t] = S.tr[k < kTile ? k : kTile - 1];
             }
-            double pr = live ? ck.at(c, 2) : 0.0;
+            double pr = p_blk;
 #pragma unroll
             for (int t = kCkb - 1; t >= 0; --t) {
                 ureg[t] = 0.0;
@@ -957,6 +966,7 @@ DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_
     zc = 1.0;                // z_{i+1}
     double zp2 = zr1;        // z_{i+2}
     const int64_t last_tile = ((n - 1) / kTile) * kTile;
+    double s_next = live ? ck.at(cl, 0) : 0.0;
     RepRow fb_ = rep_fetch(D, L, last_tile, n);
     for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
         rep_commit(S, fb_);
@@ -964,6 +974,8 @@ DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_
         const int64_t cfirst = tb / kCkb;
         const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
         for (int64_t c = clast; c >= cfirst; --c) {
+            const double s_blk = s_next;
+            s_next = (live && c >= 1) ? ck.at(c - 1, 0) : 0.0;
             const int64_t b0 = c * kCkb;
             const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
             if (b0 >= b1) continue;
@@ -974,7 +986,7 @@ DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_
                 const int k = (int)(b0 + t - tb);
                 xr[t] = S.tr[k < kTile ? k : kTile - 1];
             }
-            double sr = live ? ck.at(c, 0) : 0.0;
+            double sr = s_blk;
 #pragma unroll
             for (int t = 0; t < kCkb; ++t) {
                 lreg[t] = 0.0;
