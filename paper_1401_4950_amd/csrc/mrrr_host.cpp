@@ -428,7 +428,7 @@ extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const do
     double scale = o.arena_scale;
     for (int attempt = 0; attempt < 4; ++attempt) {
         Sizes sz = base_sizes(n, 1, kwork, n, scale);
-        sz.ck = o.jobz ? 3 * ((n + kCkb - 1) / kCkb) * pr.ck_stride : 1;
+        sz.ck = o.jobz ? kCkSlots * ((n + kCkb - 1) / kCkb) * pr.ck_stride : 1;
         Params P{};
         P.d = d;
         P.e = e ? e : d;
@@ -487,7 +487,7 @@ int build_plan(mrrr_handle_t h, mrrr_batched_plan_s* pl) {
         pr.ck_base = ck;
         pr.ck_slot0 = pl->noff[b];
         pr.ck_stride = nb;
-        ck += pl->opts.jobz ? 3 * ((nb + kCkb - 1) / kCkb) * nb : 0;
+        ck += pl->opts.jobz ? kCkSlots * ((nb + kCkb - 1) / kCkb) * nb : 0;
         zpack += nb * nb;
     }
     Sizes sz = base_sizes(rows, batch, rows, nmax, pl->opts.arena_scale);

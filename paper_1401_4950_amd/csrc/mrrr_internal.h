@@ -18,6 +18,7 @@ namespace mrrr {
 constexpr int kWave = 64;      // wavefront = one worker
 constexpr int kTile = 64;      // rows of a representation staged in LDS at once
 constexpr int kCkb = 16;       // rows between checkpoints of the twisted solver
+constexpr int kCkSlots = 6;    // doubles per checkpoint and eigenvalue
 constexpr int kNumQ = 3;       // 0: refine, 1: root + cluster, 2: singleton
 constexpr int kQRefine = 0, kQCluster = 1, kQSingle = 2;
 

@@ -152,7 +152,7 @@ constexpr int kPopMax = 8;
 //   T:                       d = alpha_i, dll = beta_{i-1}^2, dl = beta_{i-1}.
 // The two values the Sturm counts need come first (one 16-byte LDS read).
 struct alignas(32) QRow {
-    double d, dll, dl, pad;
+    double d, dll, dl, dl2;   // dl2 = (d l)^2 (representations only)
 };
 typedef double dv2 __attribute__((ext_vector_type(2)));
 // (d, dll) of staged row k in one 16-byte LDS read
@@ -209,7 +209,7 @@ DEV bool rep_commit(Shared& S, const RepRow& f) {
     x.d = f.d;
     x.dll = dl * f.l;
     x.dl = dl;
-    x.pad = 0.0;
+    x.dl2 = dl * dl;
     S.tr[l] = x;
     __syncthreads();
     return (f.d == 0.0 && f.l == 0.0) ||
@@ -240,7 +240,7 @@ DEV bool T_commit(Shared& S, const RepRow& f) {
     x.d = f.d;
     x.dll = f.l * f.l;
     x.dl = f.l;
-    x.pad = 0.0;
+    x.dl2 = 0.0;
     S.tr[l] = x;
     __syncthreads();
     return (f.d == 0.0 || (fabs(f.d) >= 0x1p-150 && fabs(f.d) <= 0x1p150)) &&
@@ -721,7 +721,7 @@ DEV void refine_members(Shared& S, const Params& P, const double* D, const doubl
 struct CkPtr {
     double* base;       // this lane's column of the checkpoint region
     int64_t stride;     // distance between checkpoint rows
-    DEV double& at(int64_t c, int k) const { return base[(c * 3 + k) * stride]; }
+    DEV double& at(int64_t c, int k) const { return base[(c * kCkSlots + k) * stride]; }
 };
 
 struct TwistOut {
@@ -868,6 +868,407 @@ DEV TwistOut twisted_impl(Shared& S, const double* D, const double* L, int64_t n
     return o;
 }
 
+// ------------------------------ division-free twisted factorisation (RQI)
+//
+// The transforms of Algs. 3.5 and 3.6 in the homogeneous form of negcount_rep:
+// forward s_i = u_i / v_i with
+//     w_i = d_i v_i + u_i (d+_i = w_i / v_i),  u_{i+1} = (d l^2)_i u_i - lam w_i,  v_{i+1} = w_i,
+// backward p_i = x_i / y_i with
+//     Om_{i+1} = (d l^2)_i y_{i+1} + x_{i+1} (omega_{i+1} = Om / y_{i+1}),
+//     x_i = d_i x_{i+1} - lam Om_{i+1},  y_i = Om_{i+1}.
+// Telescoping the products of lplus_i = (d l)_i v_i / w_i and
+// uminus_i = (d l)_i y_{i+1} / y_i gives the running sums of Alg. 3.7's
+// solution without quotients: h_i = E_i / v_i^2 with
+// E_{i+1} = (d l)_i^2 E_i + w_i^2 (E_0 = 1), and g_i = F_i / y_i^2 with
+// F_i = (d l)_i^2 F_{i+1} + y_i^2 (F_{n-1} = 1).  The twist index minimises
+// |gamma_i| = |u_i Om_{i+1} + d_i x_{i+1} v_i| / |v_i Om_{i+1}|, ranked with the
+// hardware reciprocal; gamma_r, h_r and g_r are then recomputed at r alone
+// with IEEE quotients.  The eigenvector is division-free too: below r,
+// z_i = v_i Y_i with Y_i = -(d l)_i Y_{i+1}; above r, z_k = yh_k X_k with
+// X_k = -(d l)_{k-1} X_{k-1}, where yh_k is y_k before its rescaling.
+//
+// (u, v, E) is scaled by a power of two (v into [1/2, 1)) after every row
+// i = 7 mod 8, (x, y, F) after every row i = 0 mod 8, always at the same rows,
+// so that the checkpoints -- (u, v, E) entering row 16c and (x, y, F) at the
+// top of block c, 6 doubles per 16 rows -- restart either recurrence exactly.
+// The range checks of negcount_rep (data, lam, every w and Om at least
+// 2^-800, finite states, h and g at least 1/2) send a lane to the guarded
+// quotient form, for its factorisation and its eigenvector both.
+
+DEV void hom_fwd_scale(double& u, double& v, double& E) {
+    const int ex = __builtin_amdgcn_frexp_exp(v);
+    u = __builtin_ldexp(u, -ex);
+    v = __builtin_ldexp(v, -ex);
+    E = __builtin_ldexp(E, -2 * ex);
+}
+DEV int hom_bwd_scale(double& x, double& y, double& F) {
+    const int ex = __builtin_amdgcn_frexp_exp(y);
+    x = __builtin_ldexp(x, -ex);
+    y = __builtin_ldexp(y, -ex);
+    F = __builtin_ldexp(F, -2 * ex);
+    return ex;
+}
+DEV void row_data(const double* D, const double* L, int64_t n, int64_t i, double& d, double& dll, double& dl,
+                  double& dl2) {
+    d = D[i];
+    const double l = (i < n - 1) ? L[i] : 0.0;
+    dl = d * l;
+    dll = dl * l;
+    dl2 = dl * dl;
+}
+
+DEV TwistOut twisted_hom(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
+                         const CkPtr& ck, int64_t& steps) {
+    TwistOut o;
+    // ---- forward
+    double u = -lam, v = 1.0, E = 1.0, mw = 1.0;
+    double wl = 0.0, vl = 1.0;     // w_{n-1}, v_{n-1}
+    unsigned B = 0, Bold = 0;
+    int cnt = 0;
+    bool data_ok = true;
+    RepRow f = rep_fetch(D, L, 0, n);
+    for (int64_t base = 0; base < n; base += kTile) {
+        data_ok &= (__ballot(!rep_commit(S, f)) == 0ull);
+        if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
+        if (base + kTile < n) {
+            // a whole tile that does not hold the last row
+            QRow cur[kAhead], nxt[kAhead];
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k) cur[k] = S.tr[k];
+#pragma unroll
+            for (int g = 0; g < kTile / kAhead; ++g) {
+                if (g + 1 < kTile / kAhead) {
+#pragma unroll
+                    for (int k = 0; k < kAhead; ++k) nxt[k] = S.tr[(g + 1) * kAhead + k];
+                }
+#pragma unroll
+                for (int k = 0; k < kAhead; ++k) {
+                    const int t = g * kAhead + k;
+                    if ((t & (kCkb - 1)) == 0 && live) {
+                        const int64_t c = (base + t) / kCkb;
+                        ck.at(c, 0) = u;
+                        ck.at(c, 1) = v;
+                        ck.at(c, 2) = E;
+                    }
+                    const double w = __builtin_fma(cur[k].d, v, u);
+                    const double p = u * cur[k].dll;
+                    B = __builtin_amdgcn_alignbit(B, hi32(w), 31);
+                    u = __builtin_fma(-lam, w, p);
+                    E = __builtin_fma(cur[k].dl2, E, w * w);
+                    v = w;
+                    mw = fmin(mw, fabs(w));
+                    if ((t & 7) == 7) hom_fwd_scale(u, v, E);
+                    if ((t & 31) == 31) {
+                        cnt += __builtin_popcount(B ^ __builtin_amdgcn_alignbit(Bold, B, 1));
+                        Bold = B;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kAhead; ++k) cur[k] = nxt[k];
+            }
+        } else {
+            const int lim = (int)(n - base);
+            for (int t = 0; t < lim; ++t) {
+                const int64_t i = base + t;
+                const QRow x = S.tr[t];
+                if ((i & (kCkb - 1)) == 0 && live) {
+                    ck.at(i / kCkb, 0) = u;
+                    ck.at(i / kCkb, 1) = v;
+                    ck.at(i / kCkb, 2) = E;
+                }
+                const double w = __builtin_fma(x.d, v, u);
+                cnt += sbit(w) ^ sbit(v);
+                mw = fmin(mw, fabs(w));
+                if (i == n - 1) {
+                    wl = w;
+                    vl = v;
+                } else {
+                    const double p = u * x.dll;
+                    u = __builtin_fma(-lam, w, p);
+                    E = __builtin_fma(x.dl2, E, w * w);
+                    v = w;
+                    if ((i & 7) == 7) hom_fwd_scale(u, v, E);
+                }
+            }
+        }
+    }
+    steps += n;
+    // ---- backward, with the argmin of |gamma|
+    const int64_t cl = (n - 1) / kCkb;
+    double x = D[n - 1] - lam, y = 1.0, F = 1.0;
+    if (live) {
+        ck.at(cl, 3) = x;
+        ck.at(cl, 4) = y;
+        ck.at(cl, 5) = F;
+    }
+    double best = fabs(wl) * __builtin_amdgcn_rcp(fabs(vl));   // gamma_{n-1} = d+_{n-1}
+    int r = (int)(n - 1);
+    const int64_t last_tile = ((n - 1) / kTile) * kTile;
+    RepRow fb_ = rep_fetch(D, L, last_tile, n);
+    double u_next = live ? ck.at(cl, 0) : 0.0, v_next = live ? ck.at(cl, 1) : 1.0;
+    for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
+        rep_commit(S, fb_);
+        if (tb - kTile >= 0) fb_ = rep_fetch(D, L, tb - kTile, n);
+        const int64_t cfirst = tb / kCkb;
+        const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
+        for (int64_t c = clast; c >= cfirst; --c) {
+            double uu = u_next, vv = v_next;
+            u_next = (live && c >= 1) ? ck.at(c - 1, 0) : 0.0;
+            v_next = (live && c >= 1) ? ck.at(c - 1, 1) : 1.0;
+            const int64_t b0 = c * kCkb;
+            const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);   // rows [b0, b1)
+            if (b0 >= b1) continue;
+            if (c < cl && live) {
+                ck.at(c, 3) = x;
+                ck.at(c, 4) = y;
+                ck.at(c, 5) = F;
+            }
+            QRow xr[kCkb];
+#pragma unroll
+            for (int t = 0; t < kCkb; ++t) {
+                const int k = (int)(b0 + t - tb);
+                xr[t] = S.tr[k < kTile ? k : kTile - 1];
+            }
+            // the block's forward states, entering each row
+            double ur[kCkb], vr[kCkb];
+#pragma unroll
+            for (int t = 0; t < kCkb; ++t) {
+                ur[t] = uu;
+                vr[t] = vv;
+                if (b0 + t < b1) {
+                    const double w = __builtin_fma(xr[t].d, vv, uu);
+                    const double p = uu * xr[t].dll;
+                    uu = __builtin_fma(-lam, w, p);
+                    vv = w;
+                    if ((t & 7) == 7) {
+                        const int ex = __builtin_amdgcn_frexp_exp(vv);
+                        uu = __builtin_ldexp(uu, -ex);
+                        vv = __builtin_ldexp(vv, -ex);
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = kCkb - 1; t >= 0; --t) {
+                if (b0 + t < b1) {
+                    const double om = __builtin_fma(xr[t].dll, y, x);
+                    const double m = xr[t].d * x;
+                    const double num = __builtin_fma(ur[t], om, m * vr[t]);
+                    const double den = vr[t] * om;
+                    const double ga = fabs(num) * __builtin_amdgcn_rcp(fabs(den));
+                    if (ga <= best) {
+                        best = ga;
+                        r = (int)(b0 + t);
+                    }
+                    x = __builtin_fma(-lam, om, m);
+                    F = __builtin_fma(xr[t].dl2, F, om * om);
+                    y = om;
+                    mw = fmin(mw, fabs(om));
+                    if ((t & 7) == 0) hom_bwd_scale(x, y, F);
+                }
+            }
+        }
+    }
+    steps += 2 * n;
+    // ---- gamma_r, h_r, g_r at r alone, IEEE quotients
+    double gam = wl / vl, hr = E / (vl * vl), gr = 1.0;
+    if (live && r < n - 1) {
+        const int64_t c = r / kCkb;
+        double uu = ck.at(c, 0), vv = ck.at(c, 1), EE = ck.at(c, 2);
+        double d, dll, dl, dl2;
+        for (int64_t i = c * kCkb; i < r; ++i) {
+            row_data(D, L, n, i, d, dll, dl, dl2);
+            const double w = __builtin_fma(d, vv, uu);
+            const double p = uu * dll;
+            uu = __builtin_fma(-lam, w, p);
+            EE = __builtin_fma(dl2, EE, w * w);
+            vv = w;
+            if ((i & 7) == 7) hom_fwd_scale(uu, vv, EE);
+        }
+        const int64_t b1 = (c * kCkb + kCkb) < (n - 1) ? (c * kCkb + kCkb) : (n - 1);
+        double xx = ck.at(c, 3), yy = ck.at(c, 4), FF = ck.at(c, 5);
+        for (int64_t i = b1 - 1; i > r; --i) {
+            row_data(D, L, n, i, d, dll, dl, dl2);
+            const double om = __builtin_fma(dll, yy, xx);
+            xx = __builtin_fma(-lam, om, d * xx);
+            FF = __builtin_fma(dl2, FF, om * om);
+            yy = om;
+            if ((i & 7) == 0) hom_bwd_scale(xx, yy, FF);
+        }
+        row_data(D, L, n, r, d, dll, dl, dl2);
+        const double om = __builtin_fma(dll, yy, xx);
+        const double m = d * xx;
+        gam = __builtin_fma(uu, om, m * vv) / (vv * om);
+        hr = EE / (vv * vv);
+        gr = __builtin_fma(dl2, FF, om * om) / (om * om);
+    }
+    o.neg = cnt;
+    o.r = r;
+    o.gam = gam;
+    o.nrm2 = hr + gr - 1.0;
+    const bool fin = __builtin_isfinite(u) && __builtin_isfinite(v) && __builtin_isfinite(E) &&
+                     __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(F) &&
+                     __builtin_isfinite(o.nrm2) && __builtin_isfinite(gam);
+    o.bad = (live && (!data_ok || !hom_sigma_ok(lam) || !(mw >= kHomState) || !fin || !(hr >= 0.5) ||
+                      !(gr >= 0.5))) ? 1 : 0;
+    o.guarded = 0;
+    return o;
+}
+
+// Alg. 3.7's N_r^T z = e_r in the division-free form (see twisted_hom), from
+// the checkpoints of the lane's accepted factorisation: z_r = 1; per 16-row
+// block the states are recomputed in registers, then the solution runs
+// through the block.  Values scaled by `scale` go to zcol[row] when `write`;
+// the sum of squares is returned.
+DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live, int r,
+                            double scale, const CkPtr& ck, double* zcol, bool write, int64_t& steps) {
+    double ss = live ? 1.0 : 0.0;
+    if (live && write) zcol[r] = scale;
+    const int64_t cl = (n - 1) / kCkb;
+    // ---- upward: z_k = yh_k X_k for k = r+1 .. n-1
+    double X = 0.0, dlprev = 0.0;
+    bool up = false;          // X holds X_{k-1}
+    {
+        double x_next = live ? ck.at(0, 3) : 0.0, y_next = live ? ck.at(0, 4) : 1.0;
+        RepRow fu = rep_fetch(D, L, 0, n);
+        for (int64_t tb = 0; tb < n; tb += kTile) {
+            rep_commit(S, fu);
+            if (tb + kTile < n) fu = rep_fetch(D, L, tb + kTile, n);
+            const int64_t cfirst = tb / kCkb;
+            const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
+            for (int64_t c = cfirst; c <= clast; ++c) {
+                double xx = x_next, yy = y_next;
+                x_next = (live && c + 1 <= cl) ? ck.at(c + 1, 3) : 0.0;
+                y_next = (live && c + 1 <= cl) ? ck.at(c + 1, 4) : 1.0;
+                const int64_t b0 = c * kCkb;
+                const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
+                if (b0 >= b1) continue;
+                QRow xr[kCkb];
+#pragma unroll
+                for (int t = 0; t < kCkb; ++t) {
+                    const int k = (int)(b0 + t - tb);
+                    xr[t] = S.tr[k < kTile ? k : kTile - 1];
+                }
+                // the block's y before rescaling, and the exponents removed
+                double yh[kCkb];
+                int ex[kCkb];
+#pragma unroll
+                for (int t = kCkb - 1; t >= 0; --t) {
+                    yh[t] = 1.0;
+                    ex[t] = 0;
+                    if (b0 + t < b1) {
+                        const double om = __builtin_fma(xr[t].dll, yy, xx);
+                        xx = __builtin_fma(-lam, om, xr[t].d * xx);
+                        yy = om;
+                        yh[t] = om;
+                        if ((t & 7) == 0) {
+                            ex[t] = __builtin_amdgcn_frexp_exp(yy);
+                            xx = __builtin_ldexp(xx, -ex[t]);
+                            yy = __builtin_ldexp(yy, -ex[t]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kCkb; ++t) {
+                    const int64_t k = b0 + t;
+                    if (k < b1 && live) {
+                        if (up) {
+                            X = __builtin_ldexp(-dlprev * X, -ex[t]);
+                            const double z = yh[t] * X;
+                            ss = __builtin_fma(z, z, ss);
+                            if (write) zcol[k] = z * scale;
+                        } else if (k == r) {
+                            X = 1.0 / yh[t];
+                            up = true;
+                        }
+                    }
+                    if (k < b1) dlprev = xr[t].dl;
+                }
+            }
+        }
+        // the last row: yh_{n-1} = y_{n-1} = 1, no rescaling
+        if (live && up && n >= 2) {
+            X = -dlprev * X;
+            ss = __builtin_fma(X, X, ss);
+            if (write) zcol[n - 1] = X * scale;
+        }
+    }
+    // ---- downward: z_i = v_i Y_i for i = r-1 .. 0
+    {
+        double Y = 0.0;
+        bool down = false;        // Y holds Y_{i+1}
+        double u_next = live ? ck.at(cl, 0) : 0.0, v_next = live ? ck.at(cl, 1) : 1.0;
+        const int64_t last_tile = ((n - 1) / kTile) * kTile;
+        RepRow fb_ = rep_fetch(D, L, last_tile, n);
+        for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
+            rep_commit(S, fb_);
+            if (tb - kTile >= 0) fb_ = rep_fetch(D, L, tb - kTile, n);
+            const int64_t cfirst = tb / kCkb;
+            const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
+            for (int64_t c = clast; c >= cfirst; --c) {
+                double uu = u_next, vv = v_next;
+                u_next = (live && c >= 1) ? ck.at(c - 1, 0) : 0.0;
+                v_next = (live && c >= 1) ? ck.at(c - 1, 1) : 1.0;
+                const int64_t b0 = c * kCkb;
+                const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
+                if (b0 >= b1) {
+                    // block cl is empty when n - 1 = 16 cl: v_{n-1} is its checkpoint
+                    if (live && !down && r == n - 1) {
+                        Y = 1.0 / vv;
+                        down = true;
+                    }
+                    continue;
+                }
+                QRow xr[kCkb];
+#pragma unroll
+                for (int t = 0; t < kCkb; ++t) {
+                    const int k = (int)(b0 + t - tb);
+                    xr[t] = S.tr[k < kTile ? k : kTile - 1];
+                }
+                double vr[kCkb];
+                int ex[kCkb];
+#pragma unroll
+                for (int t = 0; t < kCkb; ++t) {
+                    vr[t] = vv;
+                    ex[t] = 0;
+                    if (b0 + t < b1) {
+                        const double w = __builtin_fma(xr[t].d, vv, uu);
+                        const double p = uu * xr[t].dll;
+                        uu = __builtin_fma(-lam, w, p);
+                        vv = w;
+                        if ((t & 7) == 7) {
+                            ex[t] = __builtin_amdgcn_frexp_exp(vv);
+                            uu = __builtin_ldexp(uu, -ex[t]);
+                            vv = __builtin_ldexp(vv, -ex[t]);
+                        }
+                    }
+                }
+                // r == n - 1: v_{n-1} is the state after the block's last row
+                if (live && !down && r == n - 1 && b1 == n - 1) {
+                    Y = 1.0 / vv;
+                    down = true;
+                }
+#pragma unroll
+                for (int t = kCkb - 1; t >= 0; --t) {
+                    const int64_t i = b0 + t;
+                    if (i < b1 && live) {
+                        if (down) {
+                            Y = __builtin_ldexp(-xr[t].dl * Y, -ex[t]);
+                            const double z = vr[t] * Y;
+                            ss = __builtin_fma(z, z, ss);
+                            if (write) zcol[i] = z * scale;
+                        } else if (i == r) {
+                            Y = 1.0 / vr[t];
+                            down = true;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    steps += 2 * n;
+    return ss;
+}
+
 // The twisted factorisation with reciprocal quotients; the lanes that met a
 // zero or infinite pivot repeat it with IEEE quotients and the guard.  Only
 // those lanes are redone: a lane's eigenvector must later be solved with the
@@ -876,8 +1277,7 @@ DEV TwistOut twisted_impl(Shared& S, const double* D, const double* L, int64_t n
 // in the same computation.
 DEV TwistOut twisted(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
                      const CkPtr& ck, int64_t& steps) {
-    TwistOut o = twisted_impl<false>(S, D, L, n, lam, live, ck, steps);
-    o.guarded = 0;
+    TwistOut o = twisted_hom(S, D, L, n, lam, live, ck, steps);
     const bool redo = live && o.bad;
     if (wave_or(redo ? 1 : 0)) {
         const TwistOut g = twisted_impl<true>(S, D, L, n, lam, redo, ck, steps);
@@ -1032,7 +1432,7 @@ DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_
 // pass, which rewrites every entry of its column.
 DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live, int r,
                         double scale, const CkPtr& ck, double* zcol, bool write, bool guarded, int64_t& steps) {
-    double ss = solve_vector_impl<false>(S, D, L, n, lam, live && !guarded, r, scale, ck, zcol, write, steps);
+    double ss = solve_vector_hom(S, D, L, n, lam, live && !guarded, r, scale, ck, zcol, write, steps);
     const bool redo = live && (guarded || __builtin_isnan(ss));
     if (wave_or(redo ? 1 : 0)) {
         const double sg = solve_vector_impl<true>(S, D, L, n, lam, redo, r, scale, ck, zcol, write, steps);
