@@ -53,11 +53,11 @@ struct DevBuf {
 };
 
 struct Workspace {
-    DevBuf probs, blocks, nodes, q[kNumQ], seq[kNumQ], lo, hi, gap, lo0, hi0, vflag, slist, arena, ck, colbuf, perm, ctl;
+    DevBuf probs, blocks, nodes, q[kNumQ], seq[kNumQ], lo, hi, gap, lo0, hi0, vflag, need, slist, arena, ck, colbuf, perm, ctl;
     void release() {
         probs.release(); blocks.release(); nodes.release();
         for (int i = 0; i < kNumQ; ++i) { q[i].release(); seq[i].release(); }
-        lo.release(); hi.release(); gap.release(); lo0.release(); hi0.release(); vflag.release(); slist.release();
+        lo.release(); hi.release(); gap.release(); lo0.release(); hi0.release(); vflag.release(); need.release(); slist.release();
         arena.release(); ck.release(); colbuf.release(); perm.release(); ctl.release();
     }
 };
@@ -224,6 +224,7 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     ENS(ws.lo0, sizeof(double) * r);
     ENS(ws.hi0, sizeof(double) * r);
     ENS(ws.vflag, r);
+    ENS(ws.need, r);
     ENS(ws.slist, sizeof(int32_t) * r);
     ENS(ws.arena, sizeof(double) * sz.arena);
     ENS(ws.ck, sizeof(double) * (size_t)std::max<int64_t>(sz.ck, 1));
@@ -246,6 +247,7 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     P.lo0 = ws.lo0.as<double>();
     P.hi0 = ws.hi0.as<double>();
     P.vflag = ws.vflag.as<uint8_t>();
+    P.need = ws.need.as<uint8_t>();
     P.slist = ws.slist.as<int32_t>();
     P.slist_cap = sz.rows;
     P.arena = ws.arena.as<double>();

@@ -147,6 +147,7 @@ struct Params {
     double* lo0;          // per slot bracket as the current node received it
     double* hi0;          //   (a deterministic snapshot for neighbour tests)
     uint8_t* vflag;       // per slot: bit0 lo verified, bit1 hi verified
+    uint8_t* need;        // per slot: bits its bracket must still shrink by (slicing)
     int32_t* slist;       // singleton lists
     int64_t slist_cap;
     double* arena;

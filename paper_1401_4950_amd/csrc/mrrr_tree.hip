@@ -1582,7 +1582,7 @@ DEV int member_bits(const Params& P, int mode, double lo, double hi) {
     // search costs about two more passes
     const bool reach = (lo <= 0.0 && hi >= 0.0) || (lo > 0.0 && lo < hi * 0x1p-8) || (hi < 0.0 && hi > lo * 0x1p-8);
     if (reach) bits += 12;
-    return bits;
+    return bits < 255 ? bits : 255;
 }
 
 DEV double slice_bpp(int s, int lanes) {   // bits per pass of an s-member slice
@@ -1591,15 +1591,13 @@ DEV double slice_bpp(int s, int lanes) {   // bits per pass of an s-member slice
     return log2((double)lg + 1.0);
 }
 
-// The cut of the 64-member chunk starting at member `base`: whether this
-// lane's member starts a slice, and the slice's size.
-DEV void slice_cut(const Params& P, int64_t sb, int b, int mode, int Pb, int qmin, int qmax, int lanes, int base,
-                   bool* start, int* size) {
+// The cut of the 64-member chunk whose lane holds a member needing `bits`
+// (members past the node's end pass cap 64): whether this lane's member
+// starts a slice under pass budget Pb, and the slice's size.
+DEV void slice_cut(int bits, bool in, int Pb, int qmin, int qmax, int lanes, bool* start, int* size) {
     const int l = lane_id();
-    const int j = base + l;
     int cap = kWave;
-    if (j <= b) {
-        const int bits = member_bits(P, mode, ld_rlx_d(P.lo + sb + j), ld_rlx_d(P.hi + sb + j));
+    if (in) {
         cap = 1;
         for (int sz = kWave; sz >= 2; sz >>= 1) {
             if ((double)Pb * slice_bpp(sz, lanes) >= (double)bits) {
@@ -1619,11 +1617,14 @@ DEV void slice_cut(const Params& P, int64_t sb, int b, int mode, int Pb, int qmi
     int q = qmax;
     while (q > qmin && mins[q] < (1 << q)) --q;
     *size = 1 << q;
-    *start = (j <= b) && ((l & ((1 << q) - 1)) == 0);
+    *start = in && ((l & ((1 << q) - 1)) == 0);
 }
 
+// The members' needs are in P.need (written with their brackets, see
+// member_bits); maxbits is the largest.  Eight pass budgets are counted in one
+// sweep over the members.
 DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64_t block_rows, int smax, int64_t sb,
-                     int lanes) {
+                     int lanes, int maxbits) {
     const int l = lane_id();
     const double share = (double)P.nworkers * (double)block_rows / (double)(P.total_rows > 0 ? P.total_rows : 1);
     const int budget = share < 1.0 ? 1 : (int)share;
@@ -1631,42 +1632,53 @@ DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64
     while ((1 << (qmin + 1)) <= P.slice_min && qmin < 6) ++qmin;
     while ((1 << (qmax + 1)) <= smax && qmax < 6) ++qmax;
     if (qmax < qmin) qmax = qmin;
-    // the hardest member alone sets the least pass budget
-    int maxbits = 0;
-    for (int base = a; base <= b; base += kWave) {
-        const int j = base + l;
-        if (j <= b) maxbits = max(maxbits, member_bits(P, mode, ld_rlx_d(P.lo + sb + j), ld_rlx_d(P.hi + sb + j)));
-    }
-    for (int o = 32; o > 0; o >>= 1) maxbits = max(maxbits, __shfl_xor(maxbits, o));
     const double best_bpp = slice_bpp(1 << qmin, lanes);
-    int Pb = (int)ceil((double)maxbits / best_bpp);
-    if (Pb < 1) Pb = 1;
-    int ns = 0;
-    for (int tries = 0; tries < 24; ++tries) {
-        ns = 0;
-        for (int base = a; base <= b; base += kWave) {
-            bool st;
-            int sz;
-            slice_cut(P, sb, b, mode, Pb, qmin, qmax, lanes, base, &st, &sz);
-            ns += __popcll(__ballot(st));
+    int P0 = (int)ceil((double)maxbits / best_bpp);
+    if (P0 < 1) P0 = 1;
+    constexpr int kTry = 8;
+    int Pb = 0, ns = 0;
+    for (int round = 0; round < 4 && Pb == 0; ++round) {
+        int pbk[kTry], nsk[kTry];
+        for (int k = 0; k < kTry; ++k) {
+            pbk[k] = P0 + (P0 * k) / 4 + k;
+            nsk[k] = 0;
         }
-        if (ns <= budget) break;
-        Pb += 1 + Pb / 4;
+        for (int base = a; base <= b; base += kWave) {
+            const int j = base + l;
+            const bool in = j <= b;
+            const int bits = in ? (int)P.need[sb + j] : 0;
+#pragma unroll
+            for (int k = 0; k < kTry; ++k) {
+                bool st;
+                int sz;
+                slice_cut(bits, in, pbk[k], qmin, qmax, lanes, &st, &sz);
+                nsk[k] += __popcll(__ballot(st));
+            }
+        }
+        for (int k = 0; k < kTry && Pb == 0; ++k) {
+            if (nsk[k] <= budget || (round == 3 && k == kTry - 1)) {
+                Pb = pbk[k];
+                ns = nsk[k];
+            }
+        }
+        P0 = pbk[kTry - 1] + 1 + pbk[kTry - 1] / 4;
     }
     if (l == 0) __hip_atomic_store(&P.nodes[node_id].pending, ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint64_t first = push_reserve(P, kQRefine, ns);
     bool ok = true;
     int done = 0;
     for (int base = a; base <= b; base += kWave) {
+        const int j = base + l;
+        const bool in = j <= b;
         bool st;
         int sz;
-        slice_cut(P, sb, b, mode, Pb, qmin, qmax, lanes, base, &st, &sz);
+        slice_cut(in ? (int)P.need[sb + j] : 0, in, Pb, qmin, qmax, lanes, &st, &sz);
         const uint64_t sm = __ballot(st);
         if (st && ok) {
             Task t;
             t.type = kTaskRefine;
             t.node = node_id;
-            t.a = base + l;
+            t.a = j;
             const int e = t.a + sz - 1;
             t.b = (e < b ? e : b) | (mode << 30);
             const int k = done + __popcll(sm & ((1ull << l) - 1ull));
@@ -1732,8 +1744,9 @@ DEV FacOut dstqds_select(Shared& S, const double* D, const double* L, int64_t n,
         ok &= (__builtin_isfinite(dp) && dp != 0.0) ? 1 : 0;
         gmax = fmax(gmax, fabs(dp));
         const Recip rc = recip(dp);
-        const double lp = quot(rc, x.dl);
-        ok &= __builtin_isfinite(lp) ? 1 : 0;
+        // l+ = (d l) / d+ overflows exactly when (d l) times the reciprocal
+        // does (up to the reciprocal's 2^-24)
+        ok &= __builtin_isfinite(x.dl * rc.r) ? 1 : 0;
         s = quot(rc, s) * x.dll - tau;
     };
     RepRow f = rep_fetch(D, L, 0, n);
@@ -2119,6 +2132,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         S.m_sig[l] = sig;
         __syncthreads();
     }
+    int maxbits = 0;
     for (int64_t j = blk.k0 + l; j <= blk.k1; j += kWave) {
         int a = 0, b = kWave;   // first point whose count reaches j
         while (a < b) {
@@ -2134,7 +2148,11 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         P.lo0[sb + j] = lo;
         P.hi0[sb + j] = hi;
         P.vflag[sb + j] = 3;
+        const int bits = member_bits(P, P.jobz ? kModeClass : kModeFull, lo, hi);
+        P.need[sb + j] = (uint8_t)bits;
+        maxbits = max(maxbits, bits);
     }
+    for (int o = 32; o > 0; o >>= 1) maxbits = max(maxbits, __shfl_xor(maxbits, o));
     if (l == 0) {
         S.info_i[2] = id;
         S.info_d[0] = mu;
@@ -2142,7 +2160,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     }
     add_stat(&P.ctl->n_nodes, 1);
     push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, blk.n,
-                P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes);
+                P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes, maxbits);
 }
 
 DEV void load_members(Shared& S, const Params& P, int64_t sb, int a, int M) {
@@ -2340,20 +2358,41 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     }
     // 3. child brackets: (lambda(1 -+ nu) - tau)(1 -+ nu), nu = 10 k_rr n eps
     //    with k_rr = 10, widened outward (Sec. 3.2.3)
+    //    (four 64-member chunks' loads in flight at once: the members'
+    //    brackets are stable since the parent was classified, and the pop
+    //    that brought this task cleared this CU's cache)
     const double nu = 100.0 * (double)n * kEps;
-    for (int j = p + l; j <= q; j += kWave) {
-        const int64_t slot = sb + j;
-        double lo = ld_rlx_d(P.lo + slot), hi = ld_rlx_d(P.hi + slot);
-        if (j == p) { lo = lo_p; hi = hi_p; }
-        if (j == q) { lo = lo_q; hi = hi_q; }
-        const double clo = grow_lo(grow_lo(lo, nu) - tau, nu);
-        const double chi = grow_hi(grow_hi(hi, nu) - tau, nu);
-        st_rlx_d(P.lo + slot, clo);
-        st_rlx_d(P.hi + slot, chi);
-        P.lo0[slot] = clo;
-        P.hi0[slot] = chi;
-        P.vflag[slot] = 0;
+    int maxbits = 0;
+    for (int base = p; base <= q; base += 4 * kWave) {
+        double lo4[4], hi4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = base + k * kWave + l;
+            lo4[k] = (j <= q) ? P.lo[sb + j] : 0.0;
+            hi4[k] = (j <= q) ? P.hi[sb + j] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = base + k * kWave + l;
+            if (j <= q) {
+                const int64_t slot = sb + j;
+                double lo = lo4[k], hi = hi4[k];
+                if (j == p) { lo = lo_p; hi = hi_p; }
+                if (j == q) { lo = lo_q; hi = hi_q; }
+                const double clo = grow_lo(grow_lo(lo, nu) - tau, nu);
+                const double chi = grow_hi(grow_hi(hi, nu) - tau, nu);
+                st_rlx_d(P.lo + slot, clo);
+                st_rlx_d(P.hi + slot, chi);
+                P.lo0[slot] = clo;
+                P.hi0[slot] = chi;
+                P.vflag[slot] = 0;
+                const int bits = member_bits(P, kModeClass, clo, chi);
+                P.need[slot] = (uint8_t)bits;
+                maxbits = max(maxbits, bits);
+            }
+        }
     }
+    for (int o = 32; o > 0; o >>= 1) maxbits = max(maxbits, __shfl_xor(maxbits, o));
     if (l == 0) {
         S.info_i[0] = par.depth;
         S.info_i[1] = unverified;
@@ -2372,7 +2411,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (l == 0) {
         __hip_atomic_fetch_max(&P.ctl->dmax, par.depth + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    push_slices(P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes);
+    push_slices(P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes, maxbits);
 }
 
 // A bundle of singletons of one node, one per lane (Alg. 4.3): Rayleigh
