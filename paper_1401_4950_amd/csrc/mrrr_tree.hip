@@ -1593,23 +1593,23 @@ DEV double slice_bpp(int s, int lanes) {   // bits per pass of an s-member slice
 
 // The cut of the 64-member chunk whose lane holds a member needing `bits`
 // (members past the node's end pass cap 64): whether this lane's member
-// starts a slice under pass budget Pb, and the slice's size.
-DEV void slice_cut(int bits, bool in, int Pb, int qmin, int qmax, int lanes, bool* start, int* size) {
+// starts a slice, and the slice's size.  bpp[k] = bits per pass of a slice
+// of 64 >> k members; Pb = the pass budget.
+DEV void slice_cut(int bits, bool in, double Pb, const double* bpp, int qmin, int qmax, bool* start, int* size) {
     const int l = lane_id();
     int cap = kWave;
     if (in) {
         cap = 1;
-        for (int sz = kWave; sz >= 2; sz >>= 1) {
-            if ((double)Pb * slice_bpp(sz, lanes) >= (double)bits) {
-                cap = sz;
-                break;
-            }
-        }
+        const double need = (double)bits / Pb;
+#pragma unroll
+        for (int k = 5; k >= 0; --k)
+            if (bpp[k] >= need) cap = kWave >> k;
     }
     // mins[q] = least capacity in the aligned block of 2^q members
     int mins[7];
     int m = cap;
     mins[0] = m;
+#pragma unroll
     for (int q = 0; q < 6; ++q) {
         m = min(m, __shfl_xor(m, 1 << q));
         mins[q + 1] = m;
@@ -1632,6 +1632,8 @@ DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64
     while ((1 << (qmin + 1)) <= P.slice_min && qmin < 6) ++qmin;
     while ((1 << (qmax + 1)) <= smax && qmax < 6) ++qmax;
     if (qmax < qmin) qmax = qmin;
+    double bpp[6];   // bits per pass of slices of 64 >> k members
+    for (int k = 0; k < 6; ++k) bpp[k] = slice_bpp(kWave >> k, lanes);
     const double best_bpp = slice_bpp(1 << qmin, lanes);
     int P0 = (int)ceil((double)maxbits / best_bpp);
     if (P0 < 1) P0 = 1;
@@ -1639,26 +1641,26 @@ DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64
     int Pb = 0, ns = 0;
     for (int round = 0; round < 4 && Pb == 0; ++round) {
         int pbk[kTry], nsk[kTry];
-        for (int k = 0; k < kTry; ++k) {
-            pbk[k] = P0 + (P0 * k) / 4 + k;
-            nsk[k] = 0;
+        for (int t = 0; t < kTry; ++t) {
+            pbk[t] = P0 + (P0 * t) / 4 + t;
+            nsk[t] = 0;
         }
         for (int base = a; base <= b; base += kWave) {
             const int j = base + l;
             const bool in = j <= b;
             const int bits = in ? (int)P.need[sb + j] : 0;
 #pragma unroll
-            for (int k = 0; k < kTry; ++k) {
+            for (int t = 0; t < kTry; ++t) {
                 bool st;
                 int sz;
-                slice_cut(bits, in, pbk[k], qmin, qmax, lanes, &st, &sz);
-                nsk[k] += __popcll(__ballot(st));
+                slice_cut(bits, in, (double)pbk[t], bpp, qmin, qmax, &st, &sz);
+                nsk[t] += __popcll(__ballot(st));
             }
         }
-        for (int k = 0; k < kTry && Pb == 0; ++k) {
-            if (nsk[k] <= budget || (round == 3 && k == kTry - 1)) {
-                Pb = pbk[k];
-                ns = nsk[k];
+        for (int t = 0; t < kTry && Pb == 0; ++t) {
+            if (nsk[t] <= budget || (round == 3 && t == kTry - 1)) {
+                Pb = pbk[t];
+                ns = nsk[t];
             }
         }
         P0 = pbk[kTry - 1] + 1 + pbk[kTry - 1] / 4;
@@ -1672,7 +1674,7 @@ DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64
         const bool in = j <= b;
         bool st;
         int sz;
-        slice_cut(in ? (int)P.need[sb + j] : 0, in, Pb, qmin, qmax, lanes, &st, &sz);
+        slice_cut(in ? (int)P.need[sb + j] : 0, in, (double)Pb, bpp, qmin, qmax, &st, &sz);
         const uint64_t sm = __ballot(st);
         if (st && ok) {
             Task t;
