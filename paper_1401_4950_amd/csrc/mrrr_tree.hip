@@ -146,6 +146,8 @@ DEV double unit_pm1(uint64_t seed, uint64_t idx) {
 
 // A worker claims up to kPopMax consecutive tasks of a long queue at once.
 constexpr int kPopMax = 8;
+// A node's refinement slices are listed in LDS before they are pushed.
+constexpr int kMaxSlices = 1024;
 
 // One staged row of a representation or of T, read by all lanes:
 //   N-representation (D, L): d = d_i, dll = d_i l_i^2, dl = d_i l_i;
@@ -177,6 +179,8 @@ struct Shared {
     double info_d[2];
     int32_t redo;                             // twisted / Getvec passes redone in IEEE form
     int32_t redo_sturm;                       // Sturm counts redone in guarded form
+    int32_t sl_a[kMaxSlices];                 // refinement slices being pushed: first member,
+    int8_t sl_q[kMaxSlices];                  //   log2 of the size
 };
 
 // Rows [base, base + 64) of an N-representation (D, L): each lane fetches one
@@ -1591,40 +1595,32 @@ DEV double slice_bpp(int s, int lanes) {   // bits per pass of an s-member slice
     return log2((double)lg + 1.0);
 }
 
-// The cut of the 64-member chunk whose lane holds a member needing `bits`
-// (members past the node's end pass cap 64): whether this lane's member
-// starts a slice, and the slice's size.  bpp[k] = bits per pass of a slice
-// of 64 >> k members; Pb = the pass budget.
-DEV void slice_cut(int bits, bool in, double Pb, const double* bpp, int qmin, int qmax, bool* start, int* size) {
-    const int l = lane_id();
-    int cap = kWave;
-    if (in) {
-        cap = 1;
-        const double need = (double)bits / Pb;
-#pragma unroll
-        for (int k = 5; k >= 0; --k)
-            if (bpp[k] >= need) cap = kWave >> k;
-    }
-    // mins[q] = least capacity in the aligned block of 2^q members
-    int mins[7];
-    int m = cap;
-    mins[0] = m;
+// The cut of a 64-member chunk.  mb[q] = the most bits any member of the
+// lane's aligned block of 2^q members needs (members past the node's end
+// need none); a block of s members fits the pass budget Pb when
+// Pb * (bits per pass of an s-member slice) covers its mb.  The lane's slice
+// is its largest fitting block (between 2^qmin and 2^qmax members).
+DEV void chunk_maxbits(int bits, int* mb) {
+    int m = bits;
+    mb[0] = m;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-        m = min(m, __shfl_xor(m, 1 << q));
-        mins[q + 1] = m;
+        m = max(m, __shfl_xor(m, 1 << q));
+        mb[q + 1] = m;
     }
+}
+DEV int slice_q(const int* mb, double Pb, const double* bpp, int qmin, int qmax) {
+    // bpp[k] is for slices of 64 >> k members, i.e. q = 6 - k
     int q = qmax;
-    while (q > qmin && mins[q] < (1 << q)) --q;
-    *size = 1 << q;
-    *start = in && ((l & ((1 << q) - 1)) == 0);
+    while (q > qmin && (double)mb[q] > Pb * bpp[6 - q]) --q;
+    return q;
 }
 
 // The members' needs are in P.need (written with their brackets, see
 // member_bits); maxbits is the largest.  Eight pass budgets are counted in one
 // sweep over the members.
-DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64_t block_rows, int smax, int64_t sb,
-                     int lanes, int maxbits) {
+DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int mode, int64_t block_rows, int smax,
+                     int64_t sb, int lanes, int maxbits) {
     const int l = lane_id();
     const double share = (double)P.nworkers * (double)block_rows / (double)(P.total_rows > 0 ? P.total_rows : 1);
     const int budget = share < 1.0 ? 1 : (int)share;
@@ -1648,13 +1644,12 @@ DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64
         for (int base = a; base <= b; base += kWave) {
             const int j = base + l;
             const bool in = j <= b;
-            const int bits = in ? (int)P.need[sb + j] : 0;
+            int mb[7];
+            chunk_maxbits(in ? (int)P.need[sb + j] : 0, mb);
 #pragma unroll
             for (int t = 0; t < kTry; ++t) {
-                bool st;
-                int sz;
-                slice_cut(bits, in, (double)pbk[t], bpp, qmin, qmax, &st, &sz);
-                nsk[t] += __popcll(__ballot(st));
+                const int q = slice_q(mb, (double)pbk[t], bpp, qmin, qmax);
+                nsk[t] += __popcll(__ballot(in && (l & ((1 << q) - 1)) == 0));
             }
         }
         for (int t = 0; t < kTry && Pb == 0; ++t) {
@@ -1666,29 +1661,38 @@ DEV void push_slices(const Params& P, int node_id, int a, int b, int mode, int64
         P0 = pbk[kTry - 1] + 1 + pbk[kTry - 1] / 4;
     }
     if (l == 0) __hip_atomic_store(&P.nodes[node_id].pending, ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t first = push_reserve(P, kQRefine, ns);
-    bool ok = true;
-    int done = 0;
+    // list the slices in LDS and push the list whenever it fills (one wait
+    // for free cells per 64 slices instead of one per 64-member chunk)
+    int listed = 0;
     for (int base = a; base <= b; base += kWave) {
         const int j = base + l;
         const bool in = j <= b;
-        bool st;
-        int sz;
-        slice_cut(in ? (int)P.need[sb + j] : 0, in, (double)Pb, bpp, qmin, qmax, &st, &sz);
+        int mb[7];
+        chunk_maxbits(in ? (int)P.need[sb + j] : 0, mb);
+        const int q = slice_q(mb, (double)Pb, bpp, qmin, qmax);
+        const bool st = in && (l & ((1 << q) - 1)) == 0;
         const uint64_t sm = __ballot(st);
-        if (st && ok) {
-            Task t;
-            t.type = kTaskRefine;
-            t.node = node_id;
-            t.a = j;
-            const int e = t.a + sz - 1;
-            t.b = (e < b ? e : b) | (mode << 30);
-            const int k = done + __popcll(sm & ((1ull << l) - 1ull));
-            ok = (k < ns) && push_fill(P, kQRefine, first + (uint64_t)k, t);
+        if (st) {
+            const int k = listed + __popcll(sm & ((1ull << l) - 1ull));
+            S.sl_a[k] = j;
+            S.sl_q[k] = (int8_t)q;
         }
-        done += __popcll(sm);
+        listed += __popcll(sm);
+        if (listed > kMaxSlices - kWave || base + kWave > b) {
+            __syncthreads();
+            push_batch(P, kQRefine, listed, [&](int k) {
+                Task t;
+                t.type = kTaskRefine;
+                t.node = node_id;
+                t.a = S.sl_a[k];
+                const int e = t.a + (1 << S.sl_q[k]) - 1;
+                t.b = (e < b ? e : b) | (mode << 30);
+                return t;
+            });
+            __syncthreads();
+            listed = 0;
+        }
     }
-    push_publish(P, kQRefine, first, ns, ok);
 }
 
 DEV int new_node(const Params& P) {   // all lanes get the id
@@ -2161,7 +2165,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         S.info_d[1] = spdiam;
     }
     add_stat(&P.ctl->n_nodes, 1);
-    push_slices(P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, blk.n,
+    push_slices(S, P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, blk.n,
                 P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes, maxbits);
 }
 
@@ -2413,7 +2417,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (l == 0) {
         __hip_atomic_fetch_max(&P.ctl->dmax, par.depth + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    push_slices(P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes, maxbits);
+    push_slices(S, P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes, maxbits);
 }
 
 // A bundle of singletons of one node, one per lane (Alg. 4.3): Rayleigh
