@@ -1827,28 +1827,26 @@ DEV void dstqds_values(const double* D, const double* L, int64_t n, double tau, 
 
 // T - mu I = L D L^T by Gaussian elimination without pivoting; sgn > 0
 // requires every pivot positive, sgn < 0 every pivot negative (a definite
-// root, Sec. 3.1.2).
-DEV FacOut factor_T(Shared& S, const double* d, const double* e, int64_t n, double sc, double mu, int sgn,
-                    bool act, double* Dd, double* Ld) {
+// root, Sec. 3.1.2).  In two passes, as for dstqds: factor_select runs one
+// candidate mu per lane without writing (quotients from the reciprocal), and
+// keeps the pivot entering every 64-row tile, [tile][lane]; factor_values
+// recomputes the winner's rows tile by tile across the lanes, bit for bit.
+DEV FacOut factor_select(Shared& S, const double* d, const double* e, int64_t n, double sc, double mu, int sgn,
+                         double* ckp) {
+    const int l = lane_id();
     double dprev = 1.0, gmax = 0.0;
     int ok = 1;
     RepRow f = T_fetch(d, e, 0, n, sc);
-    for (int64_t base = 0; base < n; base += kTile) {
+    int64_t tile = 0;
+    for (int64_t base = 0; base < n; base += kTile, ++tile) {
         T_commit(S, f);
+        ckp[tile * kWave + l] = dprev;
         if (base + kTile < n) f = T_fetch(d, e, base + kTile, n, sc);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
         for (int t = 0; t < lim; ++t) {
             const int64_t i = base + t;
             const QRow x = S.tr[t];
-            double dv;
-            if (i == 0) {
-                dv = x.d - mu;
-            } else {
-                const double lv = x.dl / dprev;
-                if (act) Ld[i - 1] = lv;
-                dv = (x.d - mu) - lv * x.dl;
-            }
-            if (act) Dd[i] = dv;
+            const double dv = (i == 0) ? x.d - mu : (x.d - mu) - quot(recip(dprev), x.dl) * x.dl;
             ok &= (__builtin_isfinite(dv) && (sgn > 0 ? dv > 0.0 : dv < 0.0)) ? 1 : 0;
             gmax = fmax(gmax, fabs(dv));
             dprev = dv;
@@ -1858,6 +1856,42 @@ DEV FacOut factor_T(Shared& S, const double* d, const double* e, int64_t n, doub
     o.ok = ok;
     o.growth = gmax;
     return o;
+}
+
+DEV void factor_values(const double* d, const double* e, int64_t n, double sc, double mu, const double* ckp, int c,
+                       double* Dd, double* Ld) {
+    const int l = lane_id();
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    for (int64_t tile = l; tile < ntiles; tile += kWave) {
+        double dprev = ckp[tile * kWave + c];
+        const int64_t base = tile * kTile;
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        for (int t0 = 0; t0 < lim; t0 += 8) {
+            double dd[8], ee[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t i = base + t0 + k;
+                dd[k] = (t0 + k < lim) ? d[i] * sc : 0.0;
+                ee[k] = (t0 + k < lim && i >= 1) ? e[i - 1] * sc : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (t0 + k < lim) {
+                    const int64_t i = base + t0 + k;
+                    double dv;
+                    if (i == 0) {
+                        dv = dd[k] - mu;
+                    } else {
+                        const double lv = quot(recip(dprev), ee[k]);
+                        Ld[i - 1] = lv;
+                        dv = (dd[k] - mu) - lv * ee[k];
+                    }
+                    Dd[i] = dv;
+                    dprev = dv;
+                }
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------- classification
@@ -2051,16 +2085,16 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         if (t1 > 0) lon = l1;
     }
     // root shift mu: just outside either end, so that T - mu I is definite
-    const int64_t off = arena_alloc(P, 4 * n);
+    // (lane 0 the left candidate, lane 1 the right one)
+    const int64_t off = arena_alloc(P, 4 * n + 128);
     if (off < 0) return;
     double* C0 = P.arena + off;
-    double* C1 = P.arena + off + 2 * n;
+    double* ckp = P.arena + off + 2 * n;   // the selection's checkpoints
     double mul = lo1 - delta, mur = hin + delta;
     int side = -1;
     for (int tr = 0; tr < 16 && side < 0; ++tr) {
         const double mu = (l == 0) ? mul : mur;
-        const FacOut f = factor_T(S, d, e, n, sc, mu, (l == 0) ? 1 : -1, l < 2,
-                                  (l == 0) ? C0 : C1, ((l == 0) ? C0 : C1) + n);
+        const FacOut f = factor_select(S, d, e, n, sc, mu, (l == 0) ? 1 : -1, ckp);
         steps += 2 * n;
         const int ok0 = __shfl(f.ok, 0), ok1 = __shfl(f.ok, 1);
         const double g0 = __shfl(f.growth, 0), g1 = __shfl(f.growth, 1);
@@ -2078,7 +2112,10 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         return;
     }
     const double mu = side ? mur : mul;
-    double* Dr = side ? C1 : C0;
+    __syncthreads();
+    factor_values(d, e, n, sc, mu, ckp, side, C0, C0 + n);
+    __syncthreads();   // the rows other lanes wrote are read below
+    double* Dr = C0;
     double* Lr = Dr + n;
     // "random" relative perturbation of every datum by at most xi*eps
     // (Alg. 3.2, line 2)
@@ -2110,7 +2147,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     if (id < 0) return;
     if (l == 0) {
         Node nd;
-        nd.data = side ? off + 2 * n : off;
+        nd.data = off;
         nd.block = bid;
         nd.depth = 0;
         nd.a = (int32_t)blk.k0;
