@@ -1125,12 +1125,13 @@ DEV TwistOut twisted_hom(Shared& S, const double* D, const double* L, int64_t n,
 // the sum of squares is returned.
 DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live, int r,
                             double scale, const CkPtr& ck, double* zcol, bool write, int64_t& steps) {
+    // The rows of one block run without branches that depend on r: every lane
+    // steps through every row and keeps its running product only on the rows
+    // of its own half; the stores and the sum of squares are masked.
     double ss = live ? 1.0 : 0.0;
-    if (live && write) zcol[r] = scale;
     const int64_t cl = (n - 1) / kCkb;
     // ---- upward: z_k = yh_k X_k for k = r+1 .. n-1
     double X = 0.0, dlprev = 0.0;
-    bool up = false;          // X holds X_{k-1}
     {
         double x_next = live ? ck.at(0, 3) : 0.0, y_next = live ? ck.at(0, 4) : 1.0;
         RepRow fu = rep_fetch(D, L, 0, n);
@@ -1155,11 +1156,13 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
                 // the block's y before rescaling, and the exponents removed
                 double yh[kCkb];
                 int ex[kCkb];
+                double yr = 1.0;
+                const int rt = r - (int)b0, nb = (int)(b1 - b0);
 #pragma unroll
                 for (int t = kCkb - 1; t >= 0; --t) {
                     yh[t] = 1.0;
                     ex[t] = 0;
-                    if (b0 + t < b1) {
+                    if (t < nb) {
                         const double om = __builtin_fma(xr[t].dll, yy, xx);
                         xx = __builtin_fma(-lam, om, xr[t].d * xx);
                         yy = om;
@@ -1170,27 +1173,25 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
                             yy = __builtin_ldexp(yy, -ex[t]);
                         }
                     }
+                    yr = (t == rt) ? yh[t] : yr;
                 }
+                if (live && rt >= 0 && rt < nb) X = 1.0 / yr;   // X_r
 #pragma unroll
                 for (int t = 0; t < kCkb; ++t) {
-                    const int64_t k = b0 + t;
-                    if (k < b1 && live) {
-                        if (up) {
-                            X = __builtin_ldexp(-dlprev * X, -ex[t]);
-                            const double z = yh[t] * X;
-                            ss = __builtin_fma(z, z, ss);
-                            if (write) zcol[k] = z * scale;
-                        } else if (k == r) {
-                            X = 1.0 / yh[t];
-                            up = true;
-                        }
+                    if (t < nb) {
+                        const bool act = live && t > rt;
+                        const double Xn = __builtin_ldexp(-dlprev * X, -ex[t]);
+                        X = act ? Xn : X;
+                        const double z = act ? yh[t] * X : 0.0;
+                        ss = __builtin_fma(z, z, ss);
+                        if (write && act) zcol[b0 + t] = z * scale;
+                        dlprev = xr[t].dl;
                     }
-                    if (k < b1) dlprev = xr[t].dl;
                 }
             }
         }
         // the last row: yh_{n-1} = y_{n-1} = 1, no rescaling
-        if (live && up && n >= 2) {
+        if (live && r < n - 1) {
             X = -dlprev * X;
             ss = __builtin_fma(X, X, ss);
             if (write) zcol[n - 1] = X * scale;
@@ -1199,7 +1200,6 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
     // ---- downward: z_i = v_i Y_i for i = r-1 .. 0
     {
         double Y = 0.0;
-        bool down = false;        // Y holds Y_{i+1}
         double u_next = live ? ck.at(cl, 0) : 0.0, v_next = live ? ck.at(cl, 1) : 1.0;
         const int64_t last_tile = ((n - 1) / kTile) * kTile;
         RepRow fb_ = rep_fetch(D, L, last_tile, n);
@@ -1216,10 +1216,7 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
                 const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
                 if (b0 >= b1) {
                     // block cl is empty when n - 1 = 16 cl: v_{n-1} is its checkpoint
-                    if (live && !down && r == n - 1) {
-                        Y = 1.0 / vv;
-                        down = true;
-                    }
+                    if (live && r == n - 1) Y = 1.0 / vv;
                     continue;
                 }
                 QRow xr[kCkb];
@@ -1230,11 +1227,14 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
                 }
                 double vr[kCkb];
                 int ex[kCkb];
+                double vrr = 1.0;
+                const int rt = r - (int)b0, nb = (int)(b1 - b0);
 #pragma unroll
                 for (int t = 0; t < kCkb; ++t) {
                     vr[t] = vv;
                     ex[t] = 0;
-                    if (b0 + t < b1) {
+                    vrr = (t == rt) ? vv : vrr;
+                    if (t < nb) {
                         const double w = __builtin_fma(xr[t].d, vv, uu);
                         const double p = uu * xr[t].dll;
                         uu = __builtin_fma(-lam, w, p);
@@ -1246,29 +1246,26 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
                         }
                     }
                 }
-                // r == n - 1: v_{n-1} is the state after the block's last row
-                if (live && !down && r == n - 1 && b1 == n - 1) {
-                    Y = 1.0 / vv;
-                    down = true;
-                }
+                // r == n - 1 with no empty last block: v_{n-1} is the state after
+                // this block's last row
+                const bool rlast = rt == nb && b1 == n - 1 && (n - 1) % kCkb != 0;
+                if (rlast) vrr = vv;
+                if (live && ((rt >= 0 && rt < nb) || rlast)) Y = 1.0 / vrr;   // Y_r
 #pragma unroll
                 for (int t = kCkb - 1; t >= 0; --t) {
-                    const int64_t i = b0 + t;
-                    if (i < b1 && live) {
-                        if (down) {
-                            Y = __builtin_ldexp(-xr[t].dl * Y, -ex[t]);
-                            const double z = vr[t] * Y;
-                            ss = __builtin_fma(z, z, ss);
-                            if (write) zcol[i] = z * scale;
-                        } else if (i == r) {
-                            Y = 1.0 / vr[t];
-                            down = true;
-                        }
+                    if (t < nb) {
+                        const bool act = live && t < rt;
+                        const double Yn = __builtin_ldexp(-xr[t].dl * Y, -ex[t]);
+                        Y = act ? Yn : Y;
+                        const double z = act ? vr[t] * Y : 0.0;
+                        ss = __builtin_fma(z, z, ss);
+                        if (write && act) zcol[b0 + t] = z * scale;
                     }
                 }
             }
         }
     }
+    if (live && write) zcol[r] = scale;
     steps += 2 * n;
     return ss;
 }
