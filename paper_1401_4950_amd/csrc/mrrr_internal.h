@@ -99,6 +99,7 @@ constexpr int kLineU64 = 32;
 struct Ctl {
     uint64_t head_[kNumQ * kLineU64];   // head of queue q at head_[q * kLineU64]
     uint64_t tail_[kNumQ * kLineU64];
+    int64_t avail_[kNumQ * kLineU64];  // published tasks no consumer has claimed yet
     int64_t pending;      // tasks pushed and not yet finished
     int64_t pad_p[kLineU64 - 1];
     int32_t error;        // first error code raised on the device
@@ -116,6 +117,7 @@ struct Ctl {
 #ifdef __HIPCC__
     __device__ __host__ uint64_t* head(int q) { return head_ + q * kLineU64; }
     __device__ __host__ uint64_t* tail(int q) { return tail_ + q * kLineU64; }
+    __device__ __host__ int64_t* avail(int q) { return avail_ + q * kLineU64; }
 #endif
 };
 

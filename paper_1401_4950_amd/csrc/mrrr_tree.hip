@@ -1450,56 +1450,56 @@ DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, 
 // pos, pos + 1 when it holds that producer's task, pos + cap once consumed.
 
 // Claims tasks at the head of queue q into out[]; returns how many (0 when
-// the queue is empty).  Head and tail are read together and a claim is tried
-// as soon as the tail is ahead (two device round trips); a failed
-// compare-and-swap returns the current head, so a retry needs no reload.
-// One task per claim while the queue is short, so that parallel work spreads
-// over the workers; about (queued / workers) tasks, up to kPopMax, when it is
-// long, which divides the traffic on the head counter.  Claimed cells that a
-// producer has reserved but not yet published are waited for (producers
-// publish reserved cells without waiting on anything but the cells).
+// the queue is empty).  A consumer first takes a share of the count of
+// published, unclaimed tasks (one fetch-and-add; a share the count did not
+// cover is given back), then its tickets at the head (a second
+// fetch-and-add).  Neither step can fail and be retried, so a burst of
+// claims costs two atomic operations each however many workers contend; a
+// compare-and-swap on the head would let only one of them through per round
+// trip.  Every ticket taken this way has been reserved by a producer, since
+// the claims never exceed the tasks published.  One task per claim while the
+// queue is short, so that parallel work spreads over the workers; about
+// (queued / workers) tasks, up to kPopMax, when it is long.  A claimed cell
+// that its producer has reserved but not yet published is waited for.
 DEV int try_pop(const Params& P, int q, Task* out) {   // one lane
     // Polling uses relaxed loads only: an acquire at agent scope invalidates
     // the L2, and idle workers poll often.  The acquire follows a claim.
     const uint64_t cap = P.qcap[q];
-    uint64_t pos = __hip_atomic_load(P.ctl->head(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint64_t tl = __hip_atomic_load(P.ctl->tail(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int spin = 0; spin < 64; ++spin) {
-        if (tl <= pos) {
-            tl = __hip_atomic_load(P.ctl->tail(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (tl <= pos) return 0;
-        }
-        const uint64_t avail = tl - pos;
-        uint64_t k = (avail + (uint64_t)P.nworkers - 1) / (uint64_t)P.nworkers;
-        k = k < 1 ? 1 : (k > (uint64_t)kPopMax ? (uint64_t)kPopMax : k);
-        if (k > 1 && avail < 2 * (uint64_t)P.nworkers) k = 1;
-        if (__hip_atomic_compare_exchange_strong(P.ctl->head(q), &pos, pos + k, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            // every claimed cell published (relaxed polls), then one
-            // acquire for the cells and the data their tasks refer to
-            for (uint64_t i = 0; i < k; ++i) {
-                const uint64_t c = (pos + i) % cap;
-                int wait = 0;
-                while (__hip_atomic_load(&P.seq[q][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos + i + 1) {
-                    if (++wait > (1 << 24)) {
-                        set_error(P, kErrInternal);
-                        return 0;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
+    int64_t* av = P.ctl->avail(q);
+    const int64_t seen = __hip_atomic_load(av, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (seen <= 0) return 0;
+    const int64_t nw = P.nworkers;
+    int64_t k = (seen + nw - 1) / nw;
+    k = k < 1 ? 1 : (k > kPopMax ? kPopMax : k);
+    if (k > 1 && seen < 2 * nw) k = 1;
+    const int64_t old = __hip_atomic_fetch_add(av, -k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t got = old >= k ? k : (old > 0 ? old : 0);
+    if (got < k) __hip_atomic_fetch_add(av, k - got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (got == 0) return 0;
+    const uint64_t pos = __hip_atomic_fetch_add(P.ctl->head(q), (uint64_t)got, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    // every claimed cell published (relaxed polls), then one acquire for the
+    // cells and the data their tasks refer to
+    for (int64_t i = 0; i < got; ++i) {
+        const uint64_t c = (pos + i) % cap;
+        int wait = 0;
+        while (__hip_atomic_load(&P.seq[q][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos + i + 1) {
+            // a producer whose push failed never publishes: the error ends the wait
+            if (++wait > (1 << 24) ||
+                ((wait & 1023) == 0 && __hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                set_error(P, kErrInternal);
+                return 0;
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            for (uint64_t i = 0; i < k; ++i) out[i] = P.q[q][(pos + i) % cap];
-            // the cells go back to the producers once the loads are done
-            __builtin_amdgcn_s_waitcnt(0);
-            for (uint64_t i = 0; i < k; ++i)
-                __hip_atomic_store(&P.seq[q][(pos + i) % cap], pos + i + cap, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            return (int)k;
+            __builtin_amdgcn_s_sleep(1);
         }
-        // pos now holds the current head
     }
-    return 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int64_t i = 0; i < got; ++i) out[i] = P.q[q][(pos + i) % cap];
+    // the cells go back to the producers once the loads are done
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int64_t i = 0; i < got; ++i)
+        __hip_atomic_store(&P.seq[q][(pos + i) % cap], pos + i + cap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (int)got;
 }
 
 // Lane 0 reserves `count` tickets; every lane fills some of the cells.  One
@@ -1538,6 +1538,9 @@ DEV bool push_publish(const Params& P, int q, uint64_t first, int count, bool ok
             __hip_atomic_store(&P.seq[q][pos % P.qcap[q]], pos + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+    // the tasks become claimable (consumers wait for the cells themselves)
+    if (__ballot(!ok) == 0ull && lane_id() == 0)
+        __hip_atomic_fetch_add(P.ctl->avail(q), (int64_t)count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (__ballot(!ok) != 0ull) {
         set_error(P, kErrNoMem);
         return false;
