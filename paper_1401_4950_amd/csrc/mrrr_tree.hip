@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "mrrr_internal.h"
 
@@ -1027,49 +1028,55 @@ DEV TwistOut twisted_hom(Shared& S, const double* D, const double* L, int64_t n,
                 ck.at(c, 4) = y;
                 ck.at(c, 5) = F;
             }
-            QRow xr[kCkb];
+            // a whole block (every block but the last) runs without row tests
+            const int nb = (int)(b1 - b0);
+            auto run = [&](auto full_t) {
+                constexpr bool kFull = decltype(full_t)::value;
+                const int kb = (int)(b0 - tb);
+                QRow xr[kCkb];
 #pragma unroll
-            for (int t = 0; t < kCkb; ++t) {
-                const int k = (int)(b0 + t - tb);
-                xr[t] = S.tr[k < kTile ? k : kTile - 1];
-            }
-            // the block's forward states, entering each row
-            double ur[kCkb], vr[kCkb];
+                for (int t = 0; t < kCkb; ++t) xr[t] = S.tr[kFull ? kb + t : (kb + t < kTile ? kb + t : kTile - 1)];
+                // the block's forward states, entering each row
+                double ur[kCkb], vr[kCkb];
 #pragma unroll
-            for (int t = 0; t < kCkb; ++t) {
-                ur[t] = uu;
-                vr[t] = vv;
-                if (b0 + t < b1) {
-                    const double w = __builtin_fma(xr[t].d, vv, uu);
-                    const double p = uu * xr[t].dll;
-                    uu = __builtin_fma(-lam, w, p);
-                    vv = w;
-                    if ((t & 7) == 7) {
-                        const int ex = __builtin_amdgcn_frexp_exp(vv);
-                        uu = __builtin_ldexp(uu, -ex);
-                        vv = __builtin_ldexp(vv, -ex);
+                for (int t = 0; t < kCkb; ++t) {
+                    ur[t] = uu;
+                    vr[t] = vv;
+                    if (kFull || t < nb) {
+                        const double w = __builtin_fma(xr[t].d, vv, uu);
+                        const double p = uu * xr[t].dll;
+                        uu = __builtin_fma(-lam, w, p);
+                        vv = w;
+                        if ((t & 7) == 7) {
+                            const int ex = __builtin_amdgcn_frexp_exp(vv);
+                            uu = __builtin_ldexp(uu, -ex);
+                            vv = __builtin_ldexp(vv, -ex);
+                        }
                     }
                 }
-            }
+                int rt = -1;
 #pragma unroll
-            for (int t = kCkb - 1; t >= 0; --t) {
-                if (b0 + t < b1) {
-                    const double om = __builtin_fma(xr[t].dll, y, x);
-                    const double m = xr[t].d * x;
-                    const double num = __builtin_fma(ur[t], om, m * vr[t]);
-                    const double den = vr[t] * om;
-                    const double ga = fabs(num) * __builtin_amdgcn_rcp(fabs(den));
-                    if (ga <= best) {
-                        best = ga;
-                        r = (int)(b0 + t);
+                for (int t = kCkb - 1; t >= 0; --t) {
+                    if (kFull || t < nb) {
+                        const double om = __builtin_fma(xr[t].dll, y, x);
+                        const double m = xr[t].d * x;
+                        const double num = __builtin_fma(ur[t], om, m * vr[t]);
+                        const double den = vr[t] * om;
+                        const double ga = fabs(num) * __builtin_amdgcn_rcp(fabs(den));
+                        const bool take = ga <= best;
+                        best = take ? ga : best;
+                        rt = take ? t : rt;
+                        x = __builtin_fma(-lam, om, m);
+                        F = __builtin_fma(xr[t].dl2, F, om * om);
+                        y = om;
+                        mw = fmin(mw, fabs(om));
+                        if ((t & 7) == 0) hom_bwd_scale(x, y, F);
                     }
-                    x = __builtin_fma(-lam, om, m);
-                    F = __builtin_fma(xr[t].dl2, F, om * om);
-                    y = om;
-                    mw = fmin(mw, fabs(om));
-                    if ((t & 7) == 0) hom_bwd_scale(x, y, F);
                 }
-            }
+                if (rt >= 0) r = (int)b0 + rt;
+            };
+            if (nb == kCkb) run(std::true_type{});
+            else run(std::false_type{});
         }
     }
     steps += 2 * n;
@@ -1147,47 +1154,52 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
                 const int64_t b0 = c * kCkb;
                 const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);
                 if (b0 >= b1) continue;
-                QRow xr[kCkb];
-#pragma unroll
-                for (int t = 0; t < kCkb; ++t) {
-                    const int k = (int)(b0 + t - tb);
-                    xr[t] = S.tr[k < kTile ? k : kTile - 1];
-                }
-                // the block's y before rescaling, and the exponents removed
-                double yh[kCkb];
-                int ex[kCkb];
-                double yr = 1.0;
                 const int rt = r - (int)b0, nb = (int)(b1 - b0);
+                // a whole block (every block but the last) runs without row tests
+                auto run = [&](auto full_t) {
+                    constexpr bool kFull = decltype(full_t)::value;
+                    const int kb = (int)(b0 - tb);
+                    QRow xr[kCkb];
 #pragma unroll
-                for (int t = kCkb - 1; t >= 0; --t) {
-                    yh[t] = 1.0;
-                    ex[t] = 0;
-                    if (t < nb) {
-                        const double om = __builtin_fma(xr[t].dll, yy, xx);
-                        xx = __builtin_fma(-lam, om, xr[t].d * xx);
-                        yy = om;
-                        yh[t] = om;
-                        if ((t & 7) == 0) {
-                            ex[t] = __builtin_amdgcn_frexp_exp(yy);
-                            xx = __builtin_ldexp(xx, -ex[t]);
-                            yy = __builtin_ldexp(yy, -ex[t]);
+                    for (int t = 0; t < kCkb; ++t) xr[t] = S.tr[kFull ? kb + t : (kb + t < kTile ? kb + t : kTile - 1)];
+                    // the block's y before rescaling, and the exponents removed
+                    double yh[kCkb];
+                    int ex[kCkb];
+                    double yr = 1.0;
+#pragma unroll
+                    for (int t = kCkb - 1; t >= 0; --t) {
+                        yh[t] = 1.0;
+                        ex[t] = 0;
+                        if (kFull || t < nb) {
+                            const double om = __builtin_fma(xr[t].dll, yy, xx);
+                            xx = __builtin_fma(-lam, om, xr[t].d * xx);
+                            yy = om;
+                            yh[t] = om;
+                            if ((t & 7) == 0) {
+                                ex[t] = __builtin_amdgcn_frexp_exp(yy);
+                                xx = __builtin_ldexp(xx, -ex[t]);
+                                yy = __builtin_ldexp(yy, -ex[t]);
+                            }
+                        }
+                        yr = (t == rt) ? yh[t] : yr;
+                    }
+                    if (live && rt >= 0 && rt < nb) X = 1.0 / yr;   // X_r
+#pragma unroll
+                    for (int t = 0; t < kCkb; ++t) {
+                        if (kFull || t < nb) {
+                            const bool act = live && t > rt;
+                            const double Xm = -dlprev * X;
+                            const double Xn = ((t & 7) == 0) ? __builtin_ldexp(Xm, -ex[t]) : Xm;
+                            X = act ? Xn : X;
+                            const double z = act ? yh[t] * X : 0.0;
+                            ss = __builtin_fma(z, z, ss);
+                            if (write && act) zcol[b0 + t] = z * scale;
+                            dlprev = xr[t].dl;
                         }
                     }
-                    yr = (t == rt) ? yh[t] : yr;
-                }
-                if (live && rt >= 0 && rt < nb) X = 1.0 / yr;   // X_r
-#pragma unroll
-                for (int t = 0; t < kCkb; ++t) {
-                    if (t < nb) {
-                        const bool act = live && t > rt;
-                        const double Xn = __builtin_ldexp(-dlprev * X, -ex[t]);
-                        X = act ? Xn : X;
-                        const double z = act ? yh[t] * X : 0.0;
-                        ss = __builtin_fma(z, z, ss);
-                        if (write && act) zcol[b0 + t] = z * scale;
-                        dlprev = xr[t].dl;
-                    }
-                }
+                };
+                if (nb == kCkb) run(std::true_type{});
+                else run(std::false_type{});
             }
         }
         // the last row: yh_{n-1} = y_{n-1} = 1, no rescaling
@@ -1219,49 +1231,53 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
                     if (live && r == n - 1) Y = 1.0 / vv;
                     continue;
                 }
-                QRow xr[kCkb];
-#pragma unroll
-                for (int t = 0; t < kCkb; ++t) {
-                    const int k = (int)(b0 + t - tb);
-                    xr[t] = S.tr[k < kTile ? k : kTile - 1];
-                }
-                double vr[kCkb];
-                int ex[kCkb];
-                double vrr = 1.0;
                 const int rt = r - (int)b0, nb = (int)(b1 - b0);
+                auto run = [&](auto full_t) {
+                    constexpr bool kFull = decltype(full_t)::value;
+                    const int kb = (int)(b0 - tb);
+                    QRow xr[kCkb];
 #pragma unroll
-                for (int t = 0; t < kCkb; ++t) {
-                    vr[t] = vv;
-                    ex[t] = 0;
-                    vrr = (t == rt) ? vv : vrr;
-                    if (t < nb) {
-                        const double w = __builtin_fma(xr[t].d, vv, uu);
-                        const double p = uu * xr[t].dll;
-                        uu = __builtin_fma(-lam, w, p);
-                        vv = w;
-                        if ((t & 7) == 7) {
-                            ex[t] = __builtin_amdgcn_frexp_exp(vv);
-                            uu = __builtin_ldexp(uu, -ex[t]);
-                            vv = __builtin_ldexp(vv, -ex[t]);
+                    for (int t = 0; t < kCkb; ++t) xr[t] = S.tr[kFull ? kb + t : (kb + t < kTile ? kb + t : kTile - 1)];
+                    double vr[kCkb];
+                    int ex[kCkb];
+                    double vrr = 1.0;
+#pragma unroll
+                    for (int t = 0; t < kCkb; ++t) {
+                        vr[t] = vv;
+                        ex[t] = 0;
+                        vrr = (t == rt) ? vv : vrr;
+                        if (kFull || t < nb) {
+                            const double w = __builtin_fma(xr[t].d, vv, uu);
+                            const double p = uu * xr[t].dll;
+                            uu = __builtin_fma(-lam, w, p);
+                            vv = w;
+                            if ((t & 7) == 7) {
+                                ex[t] = __builtin_amdgcn_frexp_exp(vv);
+                                uu = __builtin_ldexp(uu, -ex[t]);
+                                vv = __builtin_ldexp(vv, -ex[t]);
+                            }
                         }
                     }
-                }
-                // r == n - 1 with no empty last block: v_{n-1} is the state after
-                // this block's last row
-                const bool rlast = rt == nb && b1 == n - 1 && (n - 1) % kCkb != 0;
-                if (rlast) vrr = vv;
-                if (live && ((rt >= 0 && rt < nb) || rlast)) Y = 1.0 / vrr;   // Y_r
+                    // r == n - 1 with no empty last block: v_{n-1} is the state
+                    // after this block's last row
+                    const bool rlast = rt == nb && b1 == n - 1 && (n - 1) % kCkb != 0;
+                    if (rlast) vrr = vv;
+                    if (live && ((rt >= 0 && rt < nb) || rlast)) Y = 1.0 / vrr;   // Y_r
 #pragma unroll
-                for (int t = kCkb - 1; t >= 0; --t) {
-                    if (t < nb) {
-                        const bool act = live && t < rt;
-                        const double Yn = __builtin_ldexp(-xr[t].dl * Y, -ex[t]);
-                        Y = act ? Yn : Y;
-                        const double z = act ? vr[t] * Y : 0.0;
-                        ss = __builtin_fma(z, z, ss);
-                        if (write && act) zcol[b0 + t] = z * scale;
+                    for (int t = kCkb - 1; t >= 0; --t) {
+                        if (kFull || t < nb) {
+                            const bool act = live && t < rt;
+                            const double Ym = -xr[t].dl * Y;
+                            const double Yn = ((t & 7) == 7) ? __builtin_ldexp(Ym, -ex[t]) : Ym;
+                            Y = act ? Yn : Y;
+                            const double z = act ? vr[t] * Y : 0.0;
+                            ss = __builtin_fma(z, z, ss);
+                            if (write && act) zcol[b0 + t] = z * scale;
+                        }
                     }
-                }
+                };
+                if (nb == kCkb) run(std::true_type{});
+                else run(std::false_type{});
             }
         }
     }
