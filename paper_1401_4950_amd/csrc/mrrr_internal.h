@@ -26,10 +26,11 @@ enum TaskType : int32_t {
     kTaskRoot = 1,     // build the root RRR of a block and start its refinement
     kTaskRefine = 2,   // refine a slice of one node's eigenvalue brackets
     kTaskCluster = 3,  // new RRR for a cluster (Alg. 3.8), then refine its members
-    kTaskSingle = 4    // bundle of singletons of one node (Alg. 4.3 + Alg. 3.7)
+    kTaskSingle = 4,   // bundle of singletons of one node (Alg. 4.3 + Alg. 3.7)
+    kTaskHelp = 5      // idle worker lending its lanes to a cluster's end refinement
 };
 
-enum RefineMode : int32_t { kModeClass = 0, kModeFull = 1 };
+enum RefineMode : int32_t { kModeClass = 0, kModeFull = 1, kModeExact = 2 };
 
 enum ErrCode : int32_t {
     kErrNone = 0, kErrNoMem = 2, kErrNoConv = 3, kErrNotImpl = 5,

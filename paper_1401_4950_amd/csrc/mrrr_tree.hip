@@ -520,6 +520,7 @@ DEV bool bracket_done(const Params& P, int mode, double lo, double hi) {
     const double mx = fmax(fabs(lo), fabs(hi));
     const double mid = lo + 0.5 * w;
     if (!(mid > lo && mid < hi)) return true;          // no double strictly inside
+    if (mode == kModeExact) return false;               // refined down to adjacent doubles
     if (mode == kModeFull) return (w <= 2.0 * kEps * mx) || (w <= 2.0 * kSafmin);
     return w <= fmax(P.rtol * mx, 2.0 * kSafmin);       // Alg. 3.3 stopping rule
 }
@@ -1723,6 +1724,222 @@ DEV int new_node(const Params& P) {   // all lanes get the id
     return id;
 }
 
+// ------------------------------------- cooperative end refinement
+//
+// The end eigenvalues of a cluster (Alg. 3.8, line 1) are refined to full
+// accuracy before its shift can be chosen, and on a deep cluster tree that
+// refinement lies on the critical path while most workers are idle.  The
+// cluster's worker (the leader) then lends the passes to idle workers: it
+// pushes helper tasks, and each pass subdivides both end brackets into
+// 32 M + 1 parts for the M workers that have joined (32 points per end and
+// worker), instead of 33 parts.  Every point a worker evaluates carries its
+// own count, so whatever it merges is a valid bracket end; the leader waits
+// only for workers that are already running, and a helper that joins late or
+// finds the refinement finished returns at once.
+constexpr int kCoopMax = 16;                // workers per pass, the leader included
+constexpr int64_t kCoopMinRows = 4096;      // shorter passes are not worth sharing
+enum CoopWord : int {
+    kCbGen = 0,     // (pass << 8) | M while pass runs; -1 once finished
+    kCbJoined,      // helpers that have joined (their ranks are 1, 2, ...)
+    kCbArrive,      // helpers done with the current pass
+    kCbKeyLoP, kCbKeyHiP, kCbKeyLoQ, kCbKeyHiQ,   // merged bracket ends (ordered keys)
+    kCbLoP, kCbHiP, kCbLoQ, kCbHiQ,                 // the pass's brackets
+    kCbAct,         // bit 0: end p still refined, bit 1: end q
+    kCbNode, kCbP, kCbQ,
+    kCbWords = 16
+};
+constexpr int64_t kCbDone = -1;
+
+// An order-preserving map of doubles to signed 64-bit integers, so that
+// atomic min / max on the keys merge bracket ends.
+DEV int64_t okey(double x) {
+    const int64_t b = (int64_t)__double_as_longlong(x);
+    return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
+}
+DEV double okey_inv(int64_t k) {
+    return __longlong_as_double((long long)(k >= 0 ? k : (k ^ 0x7fffffffffffffffLL)));
+}
+DEV int64_t cb_ld(int64_t* cb, int w) {
+    return __hip_atomic_load(cb + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void cb_st(int64_t* cb, int w, int64_t v) {
+    __hip_atomic_store(cb + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One worker's share of a pass: lanes 0..31 take end p, lanes 32..63 end q;
+// lane t of worker `rank` evaluates point rank * 32 + t of the 32 M points
+// inside the end's bracket.  The first of its points whose count reaches j
+// bounds lambda_j from above, the point before it from below.
+DEV void coop_share(Shared& S, int64_t* cb, const double* D, const double* L, int64_t n, int rank, int M,
+                    int jp, int jq, const double* br, int act, int64_t& steps) {
+    const int l = lane_id();
+    const int e = l >> 5, t = l & 31;
+    const bool on = (act >> e) & 1;
+    const double lo = br[2 * e], hi = br[2 * e + 1];
+    const int j = e ? jq : jp;
+    const double sig = on ? msec_point(lo, hi, rank * 32 + t, 32 * M) : 0.0;
+    const int c = negcount_rep(S, D, L, n, sig);
+    steps += n * (int64_t)__popcll(__ballot(on));
+    const uint64_t half = e ? 0xffffffff00000000ull : 0x00000000ffffffffull;
+    const uint64_t g = __ballot(on && c >= j) & half;
+    const int tstar = g ? (__ffsll((unsigned long long)g) - 1 - 32 * e) : 32;
+    if (on && t == tstar)
+        __hip_atomic_fetch_min(cb + (e ? kCbKeyHiQ : kCbKeyHiP), okey(sig), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (on && t == tstar - 1)
+        __hip_atomic_fetch_max(cb + (e ? kCbKeyLoQ : kCbKeyLoP), okey(sig), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A helper task: join the cluster's end refinement at `cboff` and take a
+// share of every pass that counts it, until the leader marks it finished.
+DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
+    const int l = lane_id();
+    int64_t* cb = reinterpret_cast<int64_t*>(P.arena + cboff);
+    int64_t rank = 0;
+    if (l == 0 && cb_ld(cb, kCbGen) != kCbDone)
+        rank = 1 + __hip_atomic_fetch_add(cb + kCbJoined, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    rank = __shfl(rank, 0);
+    if (rank == 0) return;
+    const int pid = (int)cb_ld(cb, kCbNode);
+    const int jp = (int)cb_ld(cb, kCbP), jq = (int)cb_ld(cb, kCbQ);
+    const Node par = P.nodes[pid];
+    const Block blk = P.blocks[par.block];
+    const int64_t n = blk.n;
+    const double* D = P.arena + par.data;
+    const double* L = D + n;
+    const uint64_t t0 = wall_clock64();
+    int64_t last = 0;
+    for (;;) {
+        int64_t gen = 0;
+        if (l == 0) {
+            for (;;) {
+                gen = __hip_atomic_load(cb + kCbGen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (gen != last) break;
+                if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    wall_clock64() - t0 > P.timeout_ticks) {
+                    gen = kCbDone;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        gen = __shfl(gen, 0);
+        if (gen == kCbDone) return;
+        last = gen;
+        const int M = (int)(gen & 0xff);
+        if (rank >= M) continue;   // joined after this pass was laid out
+        double br[4];
+        for (int k = 0; k < 4; ++k) br[k] = __longlong_as_double((long long)cb_ld(cb, kCbLoP + k));
+        const int act = (int)cb_ld(cb, kCbAct);
+        coop_share(S, cb, D, L, n, (int)rank, M, jp, jq, br, act, steps);
+        // the merges out (every lane's atomics are complete), then the arrival
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (l == 0) __hip_atomic_fetch_add(cb + kCbArrive, (int64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The leader's side.  The brackets of ends p and q are in S.m_lo / m_hi [0]
+// and [1] (both ends verified); on return each is a pair of adjacent doubles,
+// unless false is returned (counts that were not monotone across workers),
+// and then they hold valid, possibly wider brackets for the sequential
+// refinement to finish.  Adjacent doubles are the one bracket that does not
+// depend on the points that led to it, so the shift chosen from it is the
+// same however many workers joined each pass.
+DEV bool coop_ends(Shared& S, const Params& P, int pid, const double* D, const double* L, int64_t n, int p, int q,
+                   int64_t* cb, int64_t cboff, int helpers, int64_t& steps) {
+    const int l = lane_id();
+    if (l == 0) {
+        cb_st(cb, kCbGen, 0);
+        cb_st(cb, kCbJoined, 0);
+        cb_st(cb, kCbArrive, 0);
+        cb_st(cb, kCbNode, pid);
+        cb_st(cb, kCbP, p);
+        cb_st(cb, kCbQ, q);
+    }
+    // the push's release publishes the block with the tasks
+    if (!push_batch(P, kQRefine, helpers, [&](int) {
+            Task t;
+            t.type = kTaskHelp;
+            t.node = pid;
+            t.a = (int32_t)(uint32_t)((uint64_t)cboff & 0xffffffffull);
+            t.b = (int32_t)(uint32_t)((uint64_t)cboff >> 32);
+            return t;
+        }))
+        return false;
+    // a short wait lets the first pass start with the helpers that idle
+    // workers pick up at once (they poll every few microseconds)
+    const uint64_t tw = wall_clock64();
+    int64_t joined = 0;
+    if (l == 0) {
+        for (;;) {
+            joined = cb_ld(cb, kCbJoined);
+            if (joined >= helpers || wall_clock64() - tw > 4000) break;   // 40 us of the 100 MHz clock
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    bool ok = true;
+    for (int pass = 1; pass < kMaxPass; ++pass) {
+        const double lop = S.m_lo[0], hip = S.m_hi[0], loq = S.m_lo[1], hiq = S.m_hi[1];
+        const int act = (bracket_done(P, kModeExact, lop, hip) ? 0 : 1) | (bracket_done(P, kModeExact, loq, hiq) ? 0 : 2);
+        if (act == 0) break;
+        if (l == 0) joined = cb_ld(cb, kCbJoined);
+        joined = __shfl(joined, 0);
+        const int M = 1 + (int)(joined < helpers ? joined : helpers);
+        if (l == 0) {
+            cb_st(cb, kCbArrive, 0);
+            cb_st(cb, kCbKeyLoP, okey(lop));
+            cb_st(cb, kCbKeyHiP, okey(hip));
+            cb_st(cb, kCbKeyLoQ, okey(loq));
+            cb_st(cb, kCbKeyHiQ, okey(hiq));
+            cb_st(cb, kCbLoP, __double_as_longlong(lop));
+            cb_st(cb, kCbHiP, __double_as_longlong(hip));
+            cb_st(cb, kCbLoQ, __double_as_longlong(loq));
+            cb_st(cb, kCbHiQ, __double_as_longlong(hiq));
+            cb_st(cb, kCbAct, act);
+            __hip_atomic_store(cb + kCbGen, ((int64_t)pass << 8) | M, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const double br[4] = {lop, hip, loq, hiq};
+        coop_share(S, cb, D, L, n, 0, M, p, q, br, act, steps);
+        // the helpers counted in M are running: each arrives after one count
+        int stop = 0;
+        if (l == 0) {
+            const uint64_t t1 = wall_clock64();
+            while (__hip_atomic_load(cb + kCbArrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < M - 1) {
+                if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    wall_clock64() - t1 > P.timeout_ticks) {
+                    stop = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        if (__shfl(stop, 0)) {
+            ok = false;
+            break;
+        }
+        const double nlop = okey_inv(cb_ld(cb, kCbKeyLoP)), nhip = okey_inv(cb_ld(cb, kCbKeyHiP));
+        const double nloq = okey_inv(cb_ld(cb, kCbKeyLoQ)), nhiq = okey_inv(cb_ld(cb, kCbKeyHiQ));
+        if (!(nlop < nhip && nloq < nhiq)) {
+            ok = false;
+            break;
+        }
+        if (l == 0) {
+            S.m_lo[0] = nlop;
+            S.m_hi[0] = nhip;
+            S.m_lo[1] = nloq;
+            S.m_hi[1] = nhiq;
+        }
+        __syncthreads();
+    }
+    if (l == 0) __hip_atomic_store(cb + kCbGen, kCbDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (l < 2) {
+        st_rlx_d(P.lo + S.m_slot[l], S.m_lo[l]);
+        st_rlx_d(P.hi + S.m_slot[l], S.m_hi[l]);
+    }
+    return ok;
+}
+
 DEV int64_t arena_alloc(const Params& P, int64_t count) {
     uint64_t off = 0;
     if (lane_id() == 0)
@@ -2287,6 +2504,14 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     const double* D = P.arena + par.data;
     const double* L = D + n;
     const int64_t sb = blk.row0 - 1;
+    // the new representation's D+ and L+, then the selection's checkpoints
+    // (at most n + 64 doubles), then the block of the cooperative end
+    // refinement
+    const int64_t off = arena_alloc(P, 4 * n + 128);
+    if (off < 0) return;
+    double* Cn = P.arena + off;
+    double* cks = Cn + 2 * n;
+    const int64_t cboff = off + 3 * n + 64;
     // 1. the cluster's end eigenvalues to full accuracy (Alg. 3.8, line 1)
     if (l < 2) {
         const int j = (l == 0) ? p : q;
@@ -2308,7 +2533,25 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
 #ifdef MRRR_DEBUG_TRACE
     const double dbg_lo_in = ld_rlx_d(P.lo + sb + p), dbg_hi_in = ld_rlx_d(P.hi + sb + p);
 #endif
-    refine_members(S, P, D, L, n, 2, C, steps);
+    // Long representations refine the ends down to adjacent doubles (full
+    // accuracy and a little more), alone or with idle workers' help: that
+    // bracket is the same whichever way it was reached.
+    bool ends_done = false;
+    if (n >= kCoopMinRows) C.mode = kModeExact;
+    if (n >= kCoopMinRows && C.lanes >= 32 && (S.m_flag[0] & 3) == 3 && (S.m_flag[1] & 3) == 3 &&
+        !(bracket_done(P, kModeExact, S.m_lo[0], S.m_hi[0]) && bracket_done(P, kModeExact, S.m_lo[1], S.m_hi[1]))) {
+        // helpers only from workers that are idle now: tasks pushed and not
+        // yet finished occupy (or wait for) the others
+        int64_t pend = 0;
+        if (l == 0) pend = __hip_atomic_load(&P.ctl->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pend = __shfl(pend, 0);
+        const int64_t idle = (int64_t)P.nworkers - pend;
+        const int helpers = (int)(idle / 4 < kCoopMax - 1 ? idle / 4 : kCoopMax - 1);
+        if (helpers >= 3)
+            ends_done = coop_ends(S, P, pid, D, L, n, p, q, reinterpret_cast<int64_t*>(P.arena + cboff), cboff,
+                                  helpers, steps);
+    }
+    if (!ends_done) refine_members(S, P, D, L, n, 2, C, steps);
     const double lo_p = S.m_lo[0], hi_p = S.m_hi[0];
     const double lo_q = S.m_lo[1], hi_q = S.m_hi[1];
     // gaps to the neighbours outside the cluster (shift invariant), as the
@@ -2318,11 +2561,6 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     const double rgap = ld_rlx_d(P.gap + sb + q);
     // 2. shifts just outside both ends; keep the candidate with the smaller
     //    element growth; back off while the growth is too large (Alg. 3.8)
-    // the new representation's D+ and L+, then the selection's checkpoints
-    const int64_t off = arena_alloc(P, 4 * n + 128);
-    if (off < 0) return;
-    double* Cn = P.arena + off;
-    double* cks = Cn + 2 * n;
     // All back-off levels of Alg. 3.8 are tried at once: lane 2t uses
     // tau_l(t) and lane 2t+1 tau_r(t).  Level 0 sits 100 eps |lambda|
     // outside the cluster; levels 1..T-1 back off geometrically from
@@ -2656,6 +2894,9 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
                     case kTaskRefine: task_refine(S, P, tk.node, tk.a, tk.b, steps); break;
                     case kTaskCluster: task_cluster(S, P, tk.node, tk.a, tk.b, steps); break;
                     case kTaskSingle: task_single(S, P, tk.node, tk.a, tk.b, steps); ++nsingle; break;
+                    case kTaskHelp:
+                        task_help(S, P, (int64_t)((uint64_t)(uint32_t)tk.a | ((uint64_t)(uint32_t)tk.b << 32)), steps);
+                        break;
                     default: set_error(P, kErrInternal); break;
                 }
             }

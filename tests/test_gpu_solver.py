@@ -176,6 +176,30 @@ def test_determinism():
     assert np.array_equal(w1, w2) and np.array_equal(Z1, Z2)
 
 
+def test_end_refinement_shared_with_idle_workers_is_deterministic():
+    """On a long 1-2-1 matrix the cluster ends are refined with the help of
+    idle workers (helper tasks in the trace); the number that join each pass
+    depends on timing, but the ends are refined down to adjacent doubles, so
+    two solves agree bit for bit."""
+    import torch
+    import paper_1401_4950_amd as mr
+    from paper_1401_4950_amd import _lib
+    d, e = ti.one_two_one(8000)
+    cap = 200000
+    buf = torch.zeros(cap * _lib.TRACE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    w1, Z1 = mr.eigh_tridiagonal(to_dev(d), to_dev(e), options={"trace": buf.data_ptr(), "trace_cap": cap})
+    torch.cuda.synchronize()
+    st = mr.last_stats()
+    rec = np.frombuffer(buf.cpu().numpy().tobytes(), dtype=np.dtype(_lib.TRACE_FIELDS))[: min(st["n_tasks"], cap)]
+    assert (rec["type"] == 5).sum() > 0
+    w2, Z2 = mr.eigh_tridiagonal(to_dev(d), to_dev(e))
+    torch.cuda.synchronize()
+    assert torch.equal(w1, w2) and torch.equal(Z1, Z2)
+    tn = 4.0
+    res, orth = gpu_residual_orth(d, e, w1, Z1, tn)
+    assert res <= 10 and orth <= 100, (res, orth)
+
+
 def test_stats_and_trace():
     import ctypes
     import torch
