@@ -1626,10 +1626,11 @@ DEV void chunk_maxbits(int bits, int* mb) {
         mb[q + 1] = m;
     }
 }
-DEV int slice_q(const int* mb, double Pb, const double* bpp, int qmin, int qmax) {
-    // bpp[k] is for slices of 64 >> k members, i.e. q = 6 - k
+DEV int slice_q(const int* mb, double Pb, const double* bpp, const int* cf, int qmin, int qmax) {
+    // bpp[k] and cf[k] are for slices of 64 >> k members, i.e. q = 6 - k;
+    // cf passes confirm the members' unverified bracket ends first
     int q = qmax;
-    while (q > qmin && (double)mb[q] > Pb * bpp[6 - q]) --q;
+    while (q > qmin && (double)mb[q] > (Pb - (double)cf[6 - q]) * bpp[6 - q]) --q;
     return q;
 }
 
@@ -1646,9 +1647,14 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
     while ((1 << (qmax + 1)) <= smax && qmax < 6) ++qmax;
     if (qmax < qmin) qmax = qmin;
     double bpp[6];   // bits per pass of slices of 64 >> k members
-    for (int k = 0; k < 6; ++k) bpp[k] = slice_bpp(kWave >> k, lanes);
+    int cf[6];       // passes that confirm unverified ends: one, or two with one lane a member
+    for (int k = 0; k < 6; ++k) {
+        bpp[k] = slice_bpp(kWave >> k, lanes);
+        cf[k] = ((1 << k) < lanes ? (1 << k) : lanes) >= 2 ? 1 : 2;
+    }
     const double best_bpp = slice_bpp(1 << qmin, lanes);
-    int P0 = (int)ceil((double)maxbits / best_bpp);
+    const int best_cf = ((kWave >> qmin) < lanes ? (kWave >> qmin) : lanes) >= 2 ? 1 : 2;
+    int P0 = best_cf + (int)ceil((double)maxbits / best_bpp);
     if (P0 < 1) P0 = 1;
     constexpr int kTry = 8;
     int Pb = 0, ns = 0;
@@ -1665,7 +1671,7 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
             chunk_maxbits(in ? (int)P.need[sb + j] : 0, mb);
 #pragma unroll
             for (int t = 0; t < kTry; ++t) {
-                const int q = slice_q(mb, (double)pbk[t], bpp, qmin, qmax);
+                const int q = slice_q(mb, (double)pbk[t], bpp, cf, qmin, qmax);
                 nsk[t] += __popcll(__ballot(in && (l & ((1 << q) - 1)) == 0));
             }
         }
@@ -1686,7 +1692,7 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
         const bool in = j <= b;
         int mb[7];
         chunk_maxbits(in ? (int)P.need[sb + j] : 0, mb);
-        const int q = slice_q(mb, (double)Pb, bpp, qmin, qmax);
+        const int q = slice_q(mb, (double)Pb, bpp, cf, qmin, qmax);
         const bool st = in && (l & ((1 << q) - 1)) == 0;
         const uint64_t sm = __ballot(st);
         if (st) {
