@@ -1730,29 +1730,34 @@ DEV int new_node(const Params& P) {   // all lanes get the id
     return id;
 }
 
-// ------------------------------------- cooperative end refinement
+// ------------------------------------- cooperative refinement
 //
-// The end eigenvalues of a cluster (Alg. 3.8, line 1) are refined to full
-// accuracy before its shift can be chosen, and on a deep cluster tree that
-// refinement lies on the critical path while most workers are idle.  The
-// cluster's worker (the leader) then lends the passes to idle workers: it
-// pushes helper tasks, and each pass subdivides both end brackets into
-// 32 M + 1 parts for the M workers that have joined (32 points per end and
-// worker), instead of 33 parts.  Every point a worker evaluates carries its
-// own count, so whatever it merges is a valid bracket end; the leader waits
-// only for workers that are already running, and a helper that joins late or
-// finds the refinement finished returns at once.
+// The refinement of a cluster's end eigenvalues to full accuracy (Alg. 3.8,
+// line 1) lies on the critical path of a deep cluster tree while most
+// workers are idle.  The worker that owns it (the leader) then lends its
+// passes to idle workers: it pushes helper tasks, and each
+// pass gives every unfinished member L M points for the M workers that have
+// joined (L of a worker's 64 lanes a member) instead of L.  Every point
+// carries its own count, so whatever a worker merges is a valid bracket end;
+// the leader waits only for helpers counted in the current pass, which are
+// already running, and a helper that joins late waits for the next pass or,
+// finding the refinement finished, returns at once.  The members are refined
+// to adjacent doubles, the one bracket that does not depend on which points
+// were counted, so the results do not depend on how many helpers joined.
 constexpr int kCoopMax = 16;                // workers per pass, the leader included
 constexpr int64_t kCoopMinRows = 4096;      // shorter passes are not worth sharing
 enum CoopWord : int {
-    kCbGen = 0,     // (pass << 8) | M while pass runs; -1 once finished
+    kCbGen = 0,     // (pass << 8) | M while a pass runs; -1 once finished
     kCbJoined,      // helpers that have joined (their ranks are 1, 2, ...)
     kCbArrive,      // helpers done with the current pass
-    kCbKeyLoP, kCbKeyHiP, kCbKeyLoQ, kCbKeyHiQ,   // merged bracket ends (ordered keys)
-    kCbLoP, kCbHiP, kCbLoQ, kCbHiQ,                 // the pass's brackets
-    kCbAct,         // bit 0: end p still refined, bit 1: end q
-    kCbNode, kCbP, kCbQ,
-    kCbWords = 16
+    kCbNode,        // the node whose representation is refined
+    kCbAct,         // bit m: member m still refined (64-bit mask)
+    kCbKeyLo = 8,   // [64] merged lower ends of the pass (order-preserving keys)
+    kCbKeyHi = kCbKeyLo + kWave,   // [64] merged upper ends
+    kCbLo = kCbKeyHi + kWave,      // [64] the pass's brackets
+    kCbHi = kCbLo + kWave,
+    kCbJ = kCbHi + kWave,          // [64] the members' indices
+    kCbWords = kCbJ + kWave
 };
 constexpr int64_t kCbDone = -1;
 
@@ -1772,30 +1777,39 @@ DEV void cb_st(int64_t* cb, int w, int64_t v) {
     __hip_atomic_store(cb + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One worker's share of a pass: lanes 0..31 take end p, lanes 32..63 end q;
-// lane t of worker `rank` evaluates point rank * 32 + t of the 32 M points
-// inside the end's bracket.  The first of its points whose count reaches j
+// One worker's share of a pass: the na members in `act` get Lw lanes each;
+// lane t of member a evaluates point rank * Lw + t of the Lw M points inside
+// its bracket.  The first of the member's points whose count reaches j
 // bounds lambda_j from above, the point before it from below.
 DEV void coop_share(Shared& S, int64_t* cb, const double* D, const double* L, int64_t n, int rank, int M,
-                    int jp, int jq, const double* br, int act, int64_t& steps) {
+                    uint64_t act, int64_t& steps) {
     const int l = lane_id();
-    const int e = l >> 5, t = l & 31;
-    const bool on = (act >> e) & 1;
-    const double lo = br[2 * e], hi = br[2 * e + 1];
-    const int j = e ? jq : jp;
-    const double sig = on ? msec_point(lo, hi, rank * 32 + t, 32 * M) : 0.0;
+    const int na = __popcll(act);
+    if ((act >> l) & 1ull) S.ulist[__popcll(act & ((1ull << l) - 1ull))] = l;
+    __syncthreads();
+    int Lw = 1;
+    while (Lw * 2 * na <= kWave) Lw *= 2;
+    const int a = l / Lw, t = l % Lw;
+    const bool on = a < na;
+    const int m = on ? S.ulist[a] : 0;
+    const double lo = __longlong_as_double((long long)cb_ld(cb, kCbLo + m));
+    const double hi = __longlong_as_double((long long)cb_ld(cb, kCbHi + m));
+    const int j = (int)cb_ld(cb, kCbJ + m);
+    const double sig = on ? msec_point(lo, hi, rank * Lw + t, Lw * M) : 0.0;
     const int c = negcount_rep(S, D, L, n, sig);
     steps += n * (int64_t)__popcll(__ballot(on));
-    const uint64_t half = e ? 0xffffffff00000000ull : 0x00000000ffffffffull;
-    const uint64_t g = __ballot(on && c >= j) & half;
-    const int tstar = g ? (__ffsll((unsigned long long)g) - 1 - 32 * e) : 32;
+    const int gb = a * Lw;
+    const uint64_t gmask = (Lw == 64) ? ~0ull : (((1ull << Lw) - 1ull) << (gb & 63));
+    const uint64_t g = __ballot(on && c >= j) & gmask;
+    const int tstar = g ? (__ffsll((unsigned long long)g) - 1 - gb) : Lw;
     if (on && t == tstar)
-        __hip_atomic_fetch_min(cb + (e ? kCbKeyHiQ : kCbKeyHiP), okey(sig), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_min(cb + kCbKeyHi + m, okey(sig), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (on && t == tstar - 1)
-        __hip_atomic_fetch_max(cb + (e ? kCbKeyLoQ : kCbKeyLoP), okey(sig), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_max(cb + kCbKeyLo + m, okey(sig), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
 }
 
-// A helper task: join the cluster's end refinement at `cboff` and take a
+// A helper task: join the refinement whose block is at `cboff` and take a
 // share of every pass that counts it, until the leader marks it finished.
 DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
     const int l = lane_id();
@@ -1806,11 +1820,10 @@ DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
     rank = __shfl(rank, 0);
     if (rank == 0) return;
     const int pid = (int)cb_ld(cb, kCbNode);
-    const int jp = (int)cb_ld(cb, kCbP), jq = (int)cb_ld(cb, kCbQ);
-    const Node par = P.nodes[pid];
-    const Block blk = P.blocks[par.block];
+    const Node nd = P.nodes[pid];
+    const Block blk = P.blocks[nd.block];
     const int64_t n = blk.n;
-    const double* D = P.arena + par.data;
+    const double* D = P.arena + nd.data;
     const double* L = D + n;
     const uint64_t t0 = wall_clock64();
     int64_t last = 0;
@@ -1833,34 +1846,30 @@ DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
         last = gen;
         const int M = (int)(gen & 0xff);
         if (rank >= M) continue;   // joined after this pass was laid out
-        double br[4];
-        for (int k = 0; k < 4; ++k) br[k] = __longlong_as_double((long long)cb_ld(cb, kCbLoP + k));
-        const int act = (int)cb_ld(cb, kCbAct);
-        coop_share(S, cb, D, L, n, (int)rank, M, jp, jq, br, act, steps);
+        const uint64_t act = (uint64_t)cb_ld(cb, kCbAct);
+        coop_share(S, cb, D, L, n, (int)rank, M, act, steps);
         // the merges out (every lane's atomics are complete), then the arrival
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (l == 0) __hip_atomic_fetch_add(cb + kCbArrive, (int64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// The leader's side.  The brackets of ends p and q are in S.m_lo / m_hi [0]
-// and [1] (both ends verified); on return each is a pair of adjacent doubles,
-// unless false is returned (counts that were not monotone across workers),
-// and then they hold valid, possibly wider brackets for the sequential
-// refinement to finish.  Adjacent doubles are the one bracket that does not
-// depend on the points that led to it, so the shift chosen from it is the
-// same however many workers joined each pass.
-DEV bool coop_ends(Shared& S, const Params& P, int pid, const double* D, const double* L, int64_t n, int p, int q,
-                   int64_t* cb, int64_t cboff, int helpers, int64_t& steps) {
+// The leader's side, for the nm members whose brackets are in S.m_lo / m_hi
+// (both ends verified) and indices in S.m_j.  On return each bracket is a
+// pair of adjacent doubles, unless false is returned (counts that were not
+// monotone across workers, or an error), and then the brackets are valid,
+// possibly wider, for the sequential refinement to finish.  `publish` writes
+// the final brackets to the members' slots.
+DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const double* L, int64_t n, int nm,
+                     int64_t* cb, int64_t cboff, int helpers, bool publish, int64_t& steps) {
     const int l = lane_id();
     if (l == 0) {
         cb_st(cb, kCbGen, 0);
         cb_st(cb, kCbJoined, 0);
         cb_st(cb, kCbArrive, 0);
         cb_st(cb, kCbNode, pid);
-        cb_st(cb, kCbP, p);
-        cb_st(cb, kCbQ, q);
     }
+    if (l < nm) cb_st(cb, kCbJ + l, S.m_j[l]);
     // the push's release publishes the block with the tasks
     if (!push_batch(P, kQRefine, helpers, [&](int) {
             Task t;
@@ -1884,27 +1893,27 @@ DEV bool coop_ends(Shared& S, const Params& P, int pid, const double* D, const d
     }
     bool ok = true;
     for (int pass = 1; pass < kMaxPass; ++pass) {
-        const double lop = S.m_lo[0], hip = S.m_hi[0], loq = S.m_lo[1], hiq = S.m_hi[1];
-        const int act = (bracket_done(P, kModeExact, lop, hip) ? 0 : 1) | (bracket_done(P, kModeExact, loq, hiq) ? 0 : 2);
-        if (act == 0) break;
+        const double lo = (l < nm) ? S.m_lo[l] : 0.0, hi = (l < nm) ? S.m_hi[l] : 0.0;
+        const uint64_t act = __ballot(l < nm && !bracket_done(P, kModeExact, lo, hi));
+        if (act == 0ull) break;
         if (l == 0) joined = cb_ld(cb, kCbJoined);
         joined = __shfl(joined, 0);
         const int M = 1 + (int)(joined < helpers ? joined : helpers);
+        if (l < nm) {
+            cb_st(cb, kCbKeyLo + l, okey(lo));
+            cb_st(cb, kCbKeyHi + l, okey(hi));
+            cb_st(cb, kCbLo + l, __double_as_longlong(lo));
+            cb_st(cb, kCbHi + l, __double_as_longlong(hi));
+        }
         if (l == 0) {
             cb_st(cb, kCbArrive, 0);
-            cb_st(cb, kCbKeyLoP, okey(lop));
-            cb_st(cb, kCbKeyHiP, okey(hip));
-            cb_st(cb, kCbKeyLoQ, okey(loq));
-            cb_st(cb, kCbKeyHiQ, okey(hiq));
-            cb_st(cb, kCbLoP, __double_as_longlong(lop));
-            cb_st(cb, kCbHiP, __double_as_longlong(hip));
-            cb_st(cb, kCbLoQ, __double_as_longlong(loq));
-            cb_st(cb, kCbHiQ, __double_as_longlong(hiq));
-            cb_st(cb, kCbAct, act);
-            __hip_atomic_store(cb + kCbGen, ((int64_t)pass << 8) | M, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            cb_st(cb, kCbAct, (int64_t)act);
         }
-        const double br[4] = {lop, hip, loq, hiq};
-        coop_share(S, cb, D, L, n, 0, M, p, q, br, act, steps);
+        // every lane's stores out before the pass is published
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (l == 0) __hip_atomic_store(cb + kCbGen, ((int64_t)pass << 8) | M, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        coop_share(S, cb, D, L, n, 0, M, act, steps);
         // the helpers counted in M are running: each arrives after one count
         int stop = 0;
         if (l == 0) {
@@ -1924,26 +1933,36 @@ DEV bool coop_ends(Shared& S, const Params& P, int pid, const double* D, const d
             ok = false;
             break;
         }
-        const double nlop = okey_inv(cb_ld(cb, kCbKeyLoP)), nhip = okey_inv(cb_ld(cb, kCbKeyHiP));
-        const double nloq = okey_inv(cb_ld(cb, kCbKeyLoQ)), nhiq = okey_inv(cb_ld(cb, kCbKeyHiQ));
-        if (!(nlop < nhip && nloq < nhiq)) {
+        const bool mine = l < nm && ((act >> l) & 1ull);
+        const double nlo = mine ? okey_inv(cb_ld(cb, kCbKeyLo + l)) : lo;
+        const double nhi = mine ? okey_inv(cb_ld(cb, kCbKeyHi + l)) : hi;
+        if (__ballot(mine && !(nlo < nhi)) != 0ull) {
             ok = false;
             break;
         }
-        if (l == 0) {
-            S.m_lo[0] = nlop;
-            S.m_hi[0] = nhip;
-            S.m_lo[1] = nloq;
-            S.m_hi[1] = nhiq;
+        if (mine) {
+            S.m_lo[l] = nlo;
+            S.m_hi[l] = nhi;
         }
         __syncthreads();
     }
     if (l == 0) __hip_atomic_store(cb + kCbGen, kCbDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (l < 2) {
+    if (publish && l < nm) {
         st_rlx_d(P.lo + S.m_slot[l], S.m_lo[l]);
         st_rlx_d(P.hi + S.m_slot[l], S.m_hi[l]);
     }
     return ok;
+}
+
+// Helpers from workers that are idle now: tasks pushed and not yet finished
+// occupy (or wait for) the others.  0 when too few are idle to be worth it.
+DEV int coop_helpers(const Params& P) {
+    int64_t pend = 0;
+    if (lane_id() == 0) pend = __hip_atomic_load(&P.ctl->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    pend = __shfl(pend, 0);
+    const int64_t idle = (int64_t)P.nworkers - pend;
+    const int h = (int)(idle / 4 < kCoopMax - 1 ? idle / 4 : kCoopMax - 1);
+    return h >= 3 ? h : 0;
 }
 
 DEV int64_t arena_alloc(const Params& P, int64_t count) {
@@ -2517,7 +2536,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (off < 0) return;
     double* Cn = P.arena + off;
     double* cks = Cn + 2 * n;
-    const int64_t cboff = off + 3 * n + 64;
+    const int64_t cboff = off + 3 * n + 64;   // kCbWords <= n + 64 words are left for n >= kCoopMinRows
     // 1. the cluster's end eigenvalues to full accuracy (Alg. 3.8, line 1)
     if (l < 2) {
         const int j = (l == 0) ? p : q;
@@ -2546,16 +2565,10 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (n >= kCoopMinRows) C.mode = kModeExact;
     if (n >= kCoopMinRows && C.lanes >= 32 && (S.m_flag[0] & 3) == 3 && (S.m_flag[1] & 3) == 3 &&
         !(bracket_done(P, kModeExact, S.m_lo[0], S.m_hi[0]) && bracket_done(P, kModeExact, S.m_lo[1], S.m_hi[1]))) {
-        // helpers only from workers that are idle now: tasks pushed and not
-        // yet finished occupy (or wait for) the others
-        int64_t pend = 0;
-        if (l == 0) pend = __hip_atomic_load(&P.ctl->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        pend = __shfl(pend, 0);
-        const int64_t idle = (int64_t)P.nworkers - pend;
-        const int helpers = (int)(idle / 4 < kCoopMax - 1 ? idle / 4 : kCoopMax - 1);
-        if (helpers >= 3)
-            ends_done = coop_ends(S, P, pid, D, L, n, p, q, reinterpret_cast<int64_t*>(P.arena + cboff), cboff,
-                                  helpers, steps);
+        const int helpers = coop_helpers(P);
+        if (helpers > 0)
+            ends_done = coop_refine(S, P, pid, D, L, n, 2, reinterpret_cast<int64_t*>(P.arena + cboff), cboff,
+                                    helpers, true, steps);
     }
     if (!ends_done) refine_members(S, P, D, L, n, 2, C, steps);
     const double lo_p = S.m_lo[0], hi_p = S.m_hi[0];
