@@ -1600,9 +1600,11 @@ DEV int member_bits(const Params& P, int mode, double lo, double hi) {
     const double ratio = w / tgt;
     int bits = __builtin_isfinite(ratio) ? __builtin_amdgcn_frexp_exp(ratio) : 1100;
     // a bracket that reaches zero may hold a tiny eigenvalue: the binade
-    // search costs about two more passes
+    // search costs about one more pass (a larger estimate sizes the other
+    // slices for more passes than the level takes; none leaves the hard
+    // member alone on the critical path)
     const bool reach = (lo <= 0.0 && hi >= 0.0) || (lo > 0.0 && lo < hi * 0x1p-8) || (hi < 0.0 && hi > lo * 0x1p-8);
-    if (reach) bits += 12;
+    if (reach) bits += 6;
     return bits < 255 ? bits : 255;
 }
 
