@@ -2676,21 +2676,22 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     }
     // 3. child brackets: (lambda(1 -+ nu) - tau)(1 -+ nu), nu = 10 k_rr n eps
     //    with k_rr = 10, widened outward (Sec. 3.2.3)
-    //    (four 64-member chunks' loads in flight at once: the members'
+    //    (eight 64-member chunks' loads in flight at once: the members'
     //    brackets are stable since the parent was classified, and the pop
     //    that brought this task cleared this CU's cache)
     const double nu = 100.0 * (double)n * kEps;
     int maxbits = 0;
-    for (int base = p; base <= q; base += 4 * kWave) {
-        double lo4[4], hi4[4];
+    constexpr int kChunks = 8;
+    for (int base = p; base <= q; base += kChunks * kWave) {
+        double lo4[kChunks], hi4[kChunks];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kChunks; ++k) {
             const int j = base + k * kWave + l;
             lo4[k] = (j <= q) ? P.lo[sb + j] : 0.0;
             hi4[k] = (j <= q) ? P.hi[sb + j] : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kChunks; ++k) {
             const int j = base + k * kWave + l;
             if (j <= q) {
                 const int64_t slot = sb + j;
