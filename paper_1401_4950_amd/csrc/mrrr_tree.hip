@@ -1737,82 +1737,79 @@ DEV int new_node(const Params& P) {   // all lanes get the id
 // The refinement of a cluster's end eigenvalues to full accuracy (Alg. 3.8,
 // line 1) lies on the critical path of a deep cluster tree while most
 // workers are idle.  The worker that owns it (the leader) then lends its
-// passes to idle workers: it pushes helper tasks, and each
-// pass gives every unfinished member L M points for the M workers that have
-// joined (L of a worker's 64 lanes a member) instead of L.  Every point
-// carries its own count, so whatever a worker merges is a valid bracket end;
-// the leader waits only for helpers counted in the current pass, which are
-// already running, and a helper that joins late waits for the next pass or,
-// finding the refinement finished, returns at once.  The members are refined
-// to adjacent doubles, the one bracket that does not depend on which points
-// were counted, so the results do not depend on how many helpers joined.
-constexpr int kCoopMax = 16;                // workers per pass, the leader included
+// passes to idle workers without changing them: the leader counts one pass
+// of the sequential multisection schedule (the one refine_members follows:
+// each unfinished member gets Lg points inside its bracket), and each helper
+// counts, for some of the Lg + 1 brackets that pass can leave a member in,
+// the next pass's points inside that bracket.  When every member's outcome
+// was covered and no member finished, the round advances two passes, else
+// one; either way the brackets are exactly those of the sequential schedule,
+// so the results do not depend on how many helpers joined (even where counts
+// are not monotone at the rounding level, as inside glued Wilkinson's tight
+// clusters).  The leader waits only for helpers counted in the current
+// round, which are already running; a helper that joins late waits for the
+// next round or, finding the refinement finished, returns at once.
+constexpr int kCoopMax = 66;                // workers per round, the leader included
 constexpr int64_t kCoopMinRows = 4096;      // shorter passes are not worth sharing
 enum CoopWord : int {
-    kCbGen = 0,     // (pass << 8) | M while a pass runs; -1 once finished
+    kCbGen = 0,     // (round << 8) | M while a round runs; -1 once finished
     kCbJoined,      // helpers that have joined (their ranks are 1, 2, ...)
-    kCbArrive,      // helpers done with the current pass
+    kCbArrive,      // helpers done with the current round
     kCbNode,        // the node whose representation is refined
-    kCbAct,         // bit m: member m still refined (64-bit mask)
-    kCbKeyLo = 8,   // [64] merged lower ends of the pass (order-preserving keys)
-    kCbKeyHi = kCbKeyLo + kWave,   // [64] merged upper ends
-    kCbLo = kCbKeyHi + kWave,      // [64] the pass's brackets
+    kCbAct,         // bit m: member m unfinished (64-bit mask)
+    kCbLg,          // points per member in this round's passes
+    kCbLo = 8,      // [64] the round's brackets
     kCbHi = kCbLo + kWave,
     kCbJ = kCbHi + kWave,          // [64] the members' indices
-    kCbWords = kCbJ + kWave
+    kCbRes = kCbJ + kWave,         // [128] per (member, bracket): 1 + first point reaching j; 0 not counted
+    kCbWords = kCbRes + 2 * kWave
 };
 constexpr int64_t kCbDone = -1;
 
-// An order-preserving map of doubles to signed 64-bit integers, so that
-// atomic min / max on the keys merge bracket ends.
-DEV int64_t okey(double x) {
-    const int64_t b = (int64_t)__double_as_longlong(x);
-    return b >= 0 ? b : (b ^ 0x7fffffffffffffffLL);
-}
-DEV double okey_inv(int64_t k) {
-    return __longlong_as_double((long long)(k >= 0 ? k : (k ^ 0x7fffffffffffffffLL)));
-}
 DEV int64_t cb_ld(int64_t* cb, int w) {
     return __hip_atomic_load(cb + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 DEV void cb_st(int64_t* cb, int w, int64_t v) {
     __hip_atomic_store(cb + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+DEV int coop_lg(int nu, int lanes) {   // refine_members' points per member for nu members
+    int Lg = 1;
+    while (Lg * 2 * nu <= kWave && Lg * 2 <= lanes) Lg *= 2;
+    return Lg;
+}
 
-// One worker's share of a pass: the na members in `act` get Lw lanes each;
-// lane t of member a evaluates point rank * Lw + t of the Lw M points inside
-// its bracket.  The first of the member's points whose count reaches j
-// bounds lambda_j from above, the point before it from below.
-DEV void coop_share(Shared& S, int64_t* cb, const double* D, const double* L, int64_t n, int rank, int M,
-                    uint64_t act, int64_t& steps) {
+// A helper's share of a round: branch g = (rank - 1) * (64 / Lg) + l / Lg is
+// bracket b of the a-th unfinished member; lane k of the branch counts point
+// k of the next pass inside that bracket.
+DEV void coop_branches(Shared& S, int64_t* cb, const double* D, const double* L, int64_t n, int rank,
+                       uint64_t act, int Lg, int64_t& steps) {
     const int l = lane_id();
-    const int na = __popcll(act);
+    const int nu = __popcll(act);
     if ((act >> l) & 1ull) S.ulist[__popcll(act & ((1ull << l) - 1ull))] = l;
     __syncthreads();
-    int Lw = 1;
-    while (Lw * 2 * na <= kWave) Lw *= 2;
-    const int a = l / Lw, t = l % Lw;
-    const bool on = a < na;
-    const int m = on ? S.ulist[a] : 0;
+    const int bp = kWave / Lg, nbr = nu * (Lg + 1);
+    const int g = (rank - 1) * bp + l / Lg, k = l % Lg;
+    const bool on = g < nbr;
+    const int a = on ? g / (Lg + 1) : 0, b = on ? g % (Lg + 1) : 0;
+    const int m = S.ulist[a];
     const double lo = __longlong_as_double((long long)cb_ld(cb, kCbLo + m));
     const double hi = __longlong_as_double((long long)cb_ld(cb, kCbHi + m));
     const int j = (int)cb_ld(cb, kCbJ + m);
-    const double sig = on ? msec_point(lo, hi, rank * Lw + t, Lw * M) : 0.0;
+    const double lob = (b == 0) ? lo : msec_point(lo, hi, b - 1, Lg);
+    const double hib = (b == Lg) ? hi : msec_point(lo, hi, b, Lg);
+    const double sig = on ? msec_point(lob, hib, k, Lg) : 0.0;
     const int c = negcount_rep(S, D, L, n, sig);
     steps += n * (int64_t)__popcll(__ballot(on));
-    const int gb = a * Lw;
-    const uint64_t gmask = (Lw == 64) ? ~0ull : (((1ull << Lw) - 1ull) << (gb & 63));
-    const uint64_t g = __ballot(on && c >= j) & gmask;
-    const int tstar = g ? (__ffsll((unsigned long long)g) - 1 - gb) : Lw;
-    if (on && t == tstar)
-        __hip_atomic_fetch_min(cb + kCbKeyHi + m, okey(sig), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (on && t == tstar - 1)
-        __hip_atomic_fetch_max(cb + kCbKeyLo + m, okey(sig), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int gb = (l / Lg) * Lg;
+    const uint64_t gmask = (Lg == 64) ? ~0ull : (((1ull << Lg) - 1ull) << (gb & 63));
+    const uint64_t ge = __ballot(on && c >= j) & gmask;
+    const int tstar = ge ? (__ffsll((unsigned long long)ge) - 1 - gb) : Lg;
+    if (on && k == 0) cb_st(cb, kCbRes + g, tstar + 1);
     __syncthreads();
 }
 
 // A helper task: join the refinement whose block is at `cboff` and take a
-// share of every pass that counts it, until the leader marks it finished.
+// share of every round that counts it, until the leader marks it finished.
 DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
     const int l = lane_id();
     int64_t* cb = reinterpret_cast<int64_t*>(P.arena + cboff);
@@ -1847,24 +1844,30 @@ DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
         if (gen == kCbDone) return;
         last = gen;
         const int M = (int)(gen & 0xff);
-        if (rank >= M) continue;   // joined after this pass was laid out
+        if (rank >= M) continue;   // joined after this round was laid out
         const uint64_t act = (uint64_t)cb_ld(cb, kCbAct);
-        coop_share(S, cb, D, L, n, (int)rank, M, act, steps);
-        // the merges out (every lane's atomics are complete), then the arrival
+        const int Lg = (int)cb_ld(cb, kCbLg);
+        coop_branches(S, cb, D, L, n, (int)rank, act, Lg, steps);
+        // the results out (every lane's stores are complete), then the arrival
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (l == 0) __hip_atomic_fetch_add(cb + kCbArrive, (int64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// The leader's side, for the nm members whose brackets are in S.m_lo / m_hi
-// (both ends verified) and indices in S.m_j.  On return each bracket is a
-// pair of adjacent doubles, unless false is returned (counts that were not
-// monotone across workers, or an error), and then the brackets are valid,
-// possibly wider, for the sequential refinement to finish.  `publish` writes
-// the final brackets to the members' slots.
+// The leader's side, for the nm members whose verified brackets are in
+// S.m_lo / m_hi and indices in S.m_j: refine_members' schedule in `mode`
+// with `lanes` points at most per member, to the end.  False when the
+// brackets share one interval (refine_members then starts with a joint
+// pass) or on an error; the brackets are then valid for refine_members to
+// finish.  `publish` writes the final brackets to the members' slots.
 DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const double* L, int64_t n, int nm,
-                     int64_t* cb, int64_t cboff, int helpers, bool publish, int64_t& steps) {
+                     int mode, int lanes, int64_t* cb, int64_t cboff, int helpers, bool publish, int64_t& steps) {
     const int l = lane_id();
+    {
+        int same = 1;
+        if (l < nm) same = (S.m_lo[l] == S.m_lo[0] && S.m_hi[l] == S.m_hi[0]) ? 1 : 0;
+        if (nm > 1 && __ballot(same == 0) == 0ull) return false;
+    }
     if (l == 0) {
         cb_st(cb, kCbGen, 0);
         cb_st(cb, kCbJoined, 0);
@@ -1882,7 +1885,7 @@ DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const
             return t;
         }))
         return false;
-    // a short wait lets the first pass start with the helpers that idle
+    // a short wait lets the first round start with the helpers that idle
     // workers pick up at once (they poll every few microseconds)
     const uint64_t tw = wall_clock64();
     int64_t joined = 0;
@@ -1894,28 +1897,47 @@ DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const
         }
     }
     bool ok = true;
-    for (int pass = 1; pass < kMaxPass; ++pass) {
+    for (int round = 1; round < kMaxPass; ++round) {
         const double lo = (l < nm) ? S.m_lo[l] : 0.0, hi = (l < nm) ? S.m_hi[l] : 0.0;
-        const uint64_t act = __ballot(l < nm && !bracket_done(P, kModeExact, lo, hi));
+        const uint64_t act = __ballot(l < nm && !bracket_done(P, mode, lo, hi));
         if (act == 0ull) break;
+        const int nu = __popcll(act);
+        const int Lg = coop_lg(nu, lanes);
+        const int nbr = nu * (Lg + 1);
         if (l == 0) joined = cb_ld(cb, kCbJoined);
         joined = __shfl(joined, 0);
         const int M = 1 + (int)(joined < helpers ? joined : helpers);
         if (l < nm) {
-            cb_st(cb, kCbKeyLo + l, okey(lo));
-            cb_st(cb, kCbKeyHi + l, okey(hi));
             cb_st(cb, kCbLo + l, __double_as_longlong(lo));
             cb_st(cb, kCbHi + l, __double_as_longlong(hi));
         }
+        for (int g = l; g < nbr; g += kWave) cb_st(cb, kCbRes + g, 0);
         if (l == 0) {
             cb_st(cb, kCbArrive, 0);
             cb_st(cb, kCbAct, (int64_t)act);
+            cb_st(cb, kCbLg, Lg);
         }
-        // every lane's stores out before the pass is published
+        // every lane's stores out before the round is published
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (l == 0) __hip_atomic_store(cb + kCbGen, ((int64_t)pass << 8) | M, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        coop_share(S, cb, D, L, n, 0, M, act, steps);
+        if (l == 0) __hip_atomic_store(cb + kCbGen, ((int64_t)round << 8) | M, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // this round's first pass, as refine_members counts it
+        if ((act >> l) & 1ull) S.ulist[__popcll(act & ((1ull << l) - 1ull))] = l;
+        __syncthreads();
+        const int u = l / Lg, t = l % Lg;
+        const bool valid = u < nu;
+        const int m = valid ? S.ulist[u] : 0;
+        const double mlo = S.m_lo[m], mhi = S.m_hi[m];
+        const int j = S.m_j[m];
+        const double sig = valid ? msec_point(mlo, mhi, t, Lg) : 0.0;
+        const int c = negcount_rep(S, D, L, n, sig);
+        steps += n * (int64_t)__popcll(__ballot(valid));
+        const int gb = u * Lg;
+        const uint64_t gmask = (Lg == 64) ? ~0ull : (((1ull << Lg) - 1ull) << (gb & 63));
+        const uint64_t ge = __ballot(valid && c >= j) & gmask;
+        const int tstar = ge ? (__ffsll((unsigned long long)ge) - 1 - gb) : Lg;
+        const double s_hi = __shfl(sig, gb + (tstar < Lg ? tstar : Lg - 1));
+        const double s_lo = __shfl(sig, gb + (tstar > 0 ? tstar - 1 : 0));
         // the helpers counted in M are running: each arrives after one count
         int stop = 0;
         if (l == 0) {
@@ -1935,16 +1957,30 @@ DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const
             ok = false;
             break;
         }
-        const bool mine = l < nm && ((act >> l) & 1ull);
-        const double nlo = mine ? okey_inv(cb_ld(cb, kCbKeyLo + l)) : lo;
-        const double nhi = mine ? okey_inv(cb_ld(cb, kCbKeyHi + l)) : hi;
-        if (__ballot(mine && !(nlo < nhi)) != 0ull) {
-            ok = false;
-            break;
+        // lane t == 0 of each member's group: the bracket after the first
+        // pass, and after the second where every member's outcome was counted
+        // and no member finished (else the second pass runs next round)
+        double nlo = mlo, nhi = mhi;
+        if (valid && t == 0) {
+            if (tstar < Lg) nhi = s_hi;
+            if (tstar > 0) nlo = s_lo;
         }
-        if (mine) {
-            S.m_lo[l] = nlo;
-            S.m_hi[l] = nhi;
+        const bool lead = valid && t == 0;
+        const bool fin1 = lead && bracket_done(P, mode, nlo, nhi);
+        int64_t res = 0;
+        if (lead) res = cb_ld(cb, kCbRes + u * (Lg + 1) + tstar);
+        const bool two = __ballot(fin1) == 0ull && __ballot(lead && res == 0) == 0ull;
+        if (lead && two) {
+            const int t2 = (int)res - 1;
+            const double a2 = (t2 > 0) ? msec_point(nlo, nhi, t2 - 1, Lg) : nlo;
+            const double b2 = (t2 < Lg) ? msec_point(nlo, nhi, t2, Lg) : nhi;
+            nlo = a2;
+            nhi = b2;
+        }
+        __syncthreads();
+        if (lead) {
+            S.m_lo[m] = nlo;
+            S.m_hi[m] = nhi;
         }
         __syncthreads();
     }
@@ -2569,8 +2605,8 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         !(bracket_done(P, kModeExact, S.m_lo[0], S.m_hi[0]) && bracket_done(P, kModeExact, S.m_lo[1], S.m_hi[1]))) {
         const int helpers = coop_helpers(P);
         if (helpers > 0)
-            ends_done = coop_refine(S, P, pid, D, L, n, 2, reinterpret_cast<int64_t*>(P.arena + cboff), cboff,
-                                    helpers, true, steps);
+            ends_done = coop_refine(S, P, pid, D, L, n, 2, kModeExact, C.lanes,
+                                    reinterpret_cast<int64_t*>(P.arena + cboff), cboff, helpers, true, steps);
     }
     if (!ends_done) refine_members(S, P, D, L, n, 2, C, steps);
     const double lo_p = S.m_lo[0], hi_p = S.m_hi[0];

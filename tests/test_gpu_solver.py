@@ -200,6 +200,54 @@ def test_end_refinement_shared_with_idle_workers_is_deterministic():
     assert res <= 10 and orth <= 100, (res, orth)
 
 
+@pytest.mark.parametrize("fam,n", [("glued_wilkinson", 4200), ("clement", 6000)])
+def test_shared_end_refinement_families(orc, fam, n):
+    """Long representations (helpers join the cluster ends' refinement):
+    bitwise reproducible, sampled eigenvalues against the oracle's
+    bisection, residual and orthogonality of all pairs."""
+    import torch
+    import paper_1401_4950_amd as mr
+    d, e = ti.family(fam, n, 0)
+    w1, Z1 = mr.eigh_tridiagonal(to_dev(d), to_dev(e))
+    w2, Z2 = mr.eigh_tridiagonal(to_dev(d), to_dev(e))
+    torch.cuda.synchronize()
+    assert torch.equal(w1, w2) and torch.equal(Z1, Z2)
+    idx = np.unique(np.linspace(1, n, 32).astype(int))
+    wo = np.array([orc.eigval_index(d, e, int(k)) for k in idx])
+    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
+    wh = w1.cpu().numpy()
+    assert np.max(np.abs(wh[idx - 1] - wo)) <= 4 * n * EPS * tn
+    res, orth = gpu_residual_orth(d, e, w1, Z1, tn)
+    assert res <= 10 and orth <= 100, (res, orth)
+
+
+@pytest.mark.xfail(reason="known gap: glued Wilkinson with 400 blocks (n = 8400) leaves 287 cluster representations "
+                          "whose element growth fails the test of Alg. 3.8 at every back-off level; they are accepted "
+                          "at the least growth (remark 6, counted in n_unverified_rrr) and orthogonality reaches "
+                          "~235 n eps; the envelope test of remark 3 is not implemented", strict=False)
+def test_glued_wilkinson_400_blocks_orthogonality(orc):
+    import torch
+    import paper_1401_4950_amd as mr
+    n = 8400
+    d, e = ti.family("glued_wilkinson", n, 0)
+    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e))
+    torch.cuda.synchronize()
+    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
+    res, orth = gpu_residual_orth(d, e, w, Z, tn)
+    assert res <= 10 and orth <= 100, (res, orth)
+
+
+def test_index_range_on_a_long_matrix(orc):
+    """An index range inside 1-2-1's large cluster at n = 6000 (the cluster
+    tree and the shared end refinement run as for the whole spectrum)
+    against the oracle's own solve of the same range."""
+    d, e = ti.one_two_one(6000)
+    il, iu = 2001, 2400
+    w, Z = gpu_solve(d, e, select="i", select_range=(il, iu))
+    wo, Zo = orc.solve(d, e, "index", il=il, iu=iu)
+    check_pairs(d, e, w, Z, wo, Zo, tnorm=4.0)
+
+
 def test_stats_and_trace():
     import ctypes
     import torch
