@@ -30,7 +30,7 @@ enum TaskType : int32_t {
     kTaskHelp = 5      // idle worker lending its lanes to a cluster's end refinement
 };
 
-enum RefineMode : int32_t { kModeClass = 0, kModeFull = 1, kModeExact = 2 };
+enum RefineMode : int32_t { kModeClass = 0, kModeFull = 1 };
 
 enum ErrCode : int32_t {
     kErrNone = 0, kErrNoMem = 2, kErrNoConv = 3, kErrNotImpl = 5,

@@ -520,7 +520,6 @@ DEV bool bracket_done(const Params& P, int mode, double lo, double hi) {
     const double mx = fmax(fabs(lo), fabs(hi));
     const double mid = lo + 0.5 * w;
     if (!(mid > lo && mid < hi)) return true;          // no double strictly inside
-    if (mode == kModeExact) return false;               // refined down to adjacent doubles
     if (mode == kModeFull) return (w <= 2.0 * kEps * mx) || (w <= 2.0 * kSafmin);
     return w <= fmax(P.rtol * mx, 2.0 * kSafmin);       // Alg. 3.3 stopping rule
 }
@@ -2596,16 +2595,14 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
 #ifdef MRRR_DEBUG_TRACE
     const double dbg_lo_in = ld_rlx_d(P.lo + sb + p), dbg_hi_in = ld_rlx_d(P.hi + sb + p);
 #endif
-    // Long representations refine the ends down to adjacent doubles (full
-    // accuracy and a little more), alone or with idle workers' help: that
-    // bracket is the same whichever way it was reached.
+    // long representations: with idle workers' help when there are any (the
+    // brackets are those of the sequential schedule either way)
     bool ends_done = false;
-    if (n >= kCoopMinRows) C.mode = kModeExact;
-    if (n >= kCoopMinRows && C.lanes >= 32 && (S.m_flag[0] & 3) == 3 && (S.m_flag[1] & 3) == 3 &&
-        !(bracket_done(P, kModeExact, S.m_lo[0], S.m_hi[0]) && bracket_done(P, kModeExact, S.m_lo[1], S.m_hi[1]))) {
+    if (n >= kCoopMinRows && (S.m_flag[0] & 3) == 3 && (S.m_flag[1] & 3) == 3 &&
+        !(bracket_done(P, C.mode, S.m_lo[0], S.m_hi[0]) && bracket_done(P, C.mode, S.m_lo[1], S.m_hi[1]))) {
         const int helpers = coop_helpers(P);
         if (helpers > 0)
-            ends_done = coop_refine(S, P, pid, D, L, n, 2, kModeExact, C.lanes,
+            ends_done = coop_refine(S, P, pid, D, L, n, 2, C.mode, C.lanes,
                                     reinterpret_cast<int64_t*>(P.arena + cboff), cboff, helpers, true, steps);
     }
     if (!ends_done) refine_members(S, P, D, L, n, 2, C, steps);
