@@ -178,8 +178,8 @@ def test_determinism():
 
 def test_end_refinement_shared_with_idle_workers_is_deterministic():
     """On a long 1-2-1 matrix the cluster ends are refined with the help of
-    idle workers (helper tasks in the trace); the number that join each pass
-    depends on timing, but the ends are refined down to adjacent doubles, so
+    idle workers (helper tasks in the trace); the number that join each round
+    depends on timing, but the brackets follow the sequential schedule, so
     two solves agree bit for bit."""
     import torch
     import paper_1401_4950_amd as mr
