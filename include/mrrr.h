@@ -129,6 +129,14 @@ typedef struct {
                                   guarded quotient form: a zero pivot, an overflow,
                                   or data outside the range of the division-free
                                   count (App. B) */
+    int64_t n_checked;         /* clusters whose representation passed no growth
+                                  test (at most 64 wanted columns, outermost in
+                                  their subtree): Z^T Z of their columns checked
+                                  after the tree (remark (6) on Alg. 3.8) */
+    int64_t n_reorthogonalized;/* of those, re-orthogonalised because
+                                  max |Z^T Z - I| exceeded 20 n eps */
+    int64_t n_check_failed;    /* unverified clusters left unchecked (no record
+                                  slot) or too far from orthogonal to correct */
 } mrrr_stats_t;
 
 /* Creates a handle on HIP device `device`.  The handle owns a workspace that

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrrr.so")
-SOURCES = ["mrrr_tree.hip", "mrrr_adjoint.hip", "mrrr_host.cpp"]
+SOURCES = ["mrrr_tree.hip", "mrrr_check.hip", "mrrr_adjoint.hip", "mrrr_host.cpp"]
 ARCH = os.environ.get("MRRR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
         ("n_nan_retry", ctypes.c_int64), ("qd_steps", ctypes.c_int64), ("n_tasks", ctypes.c_int64),
         ("n_singleton_tasks", ctypes.c_int64), ("n_rqi_iters", ctypes.c_int64),
         ("arena_bytes", ctypes.c_int64), ("ms", ctypes.c_double), ("tree_ms", ctypes.c_double),
-        ("n_sturm_guarded", ctypes.c_int64),
+        ("n_sturm_guarded", ctypes.c_int64), ("n_checked", ctypes.c_int64),
+        ("n_reorthogonalized", ctypes.c_int64), ("n_check_failed", ctypes.c_int64),
     ]
 
     def as_dict(self):

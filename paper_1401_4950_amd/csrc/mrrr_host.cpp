@@ -13,6 +13,7 @@
 #include "mrrr_internal.h"
 
 static_assert(sizeof(mrrr::TraceRec) == sizeof(mrrr_trace_t), "trace record layout");
+static_assert(sizeof(mrrr::CheckRec) == 64, "check record layout");
 
 namespace mrrr {
 hipError_t launch_init(const Params& P, hipStream_t s);
@@ -20,6 +21,7 @@ hipError_t launch_setup(const Params& P, hipStream_t s);
 hipError_t launch_tree(const Params& P, hipStream_t s);
 hipError_t launch_finalize(const Params& P, hipStream_t s);
 hipError_t launch_sign(const Params& P, int64_t ncols_total, hipStream_t s);
+hipError_t launch_check(const Params& P, hipStream_t s);
 hipError_t tree_occupancy(int* blocks_per_cu);
 int adjoint_run(hipStream_t s, int64_t batch, const int64_t* n_offsets_h, const int64_t* z_offsets_h,
                 const double* w, const double* Z, const double* wbar, const double* Zbar,
@@ -53,12 +55,12 @@ struct DevBuf {
 };
 
 struct Workspace {
-    DevBuf probs, blocks, nodes, q[kNumQ], seq[kNumQ], lo, hi, gap, lo0, hi0, vflag, need, slist, arena, ck, colbuf, perm, ctl;
+    DevBuf probs, blocks, nodes, q[kNumQ], seq[kNumQ], lo, hi, gap, lo0, hi0, vflag, need, slist, arena, ck, colbuf, perm, ctl, chk;
     void release() {
         probs.release(); blocks.release(); nodes.release();
         for (int i = 0; i < kNumQ; ++i) { q[i].release(); seq[i].release(); }
         lo.release(); hi.release(); gap.release(); lo0.release(); hi0.release(); vflag.release(); need.release(); slist.release();
-        arena.release(); ck.release(); colbuf.release(); perm.release(); ctl.release();
+        arena.release(); ck.release(); colbuf.release(); perm.release(); ctl.release(); chk.release();
     }
 };
 
@@ -231,6 +233,9 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     ENS(ws.colbuf, sizeof(double) * 2 * r);
     ENS(ws.perm, sizeof(int32_t) * 2 * r);
     ENS(ws.ctl, sizeof(Ctl));
+    // checked clusters are disjoint and hold two columns or more
+    const int64_t nchk = std::max<int64_t>(sz.rows / 2, 1);
+    ENS(ws.chk, sizeof(CheckRec) * (size_t)nchk);
 #undef ENS
     P.probs = ws.probs.as<Problem>();
     P.blocks = ws.blocks.as<Block>();
@@ -256,6 +261,8 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     P.colbuf = ws.colbuf.as<double>();
     P.perm = ws.perm.as<int32_t>();
     P.ctl = ws.ctl.as<Ctl>();
+    P.chk = ws.chk.as<CheckRec>();
+    P.chk_cap = nchk;
     P.total_rows = sz.rows;
     return hipSuccess;
 }
@@ -349,6 +356,9 @@ void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms, float tree_
     st->n_bisect_fallback = c.n_fallback;
     st->n_nan_retry = c.n_nan;
     st->n_sturm_guarded = c.n_sturm;
+    st->n_checked = c.n_checked;
+    st->n_reorthogonalized = c.n_repaired;
+    st->n_check_failed = c.n_check_failed;
     st->qd_steps = c.qd_steps;
     st->n_tasks = c.n_tasks;
     st->n_singleton_tasks = c.n_single;
@@ -367,6 +377,7 @@ hipError_t enqueue_solve(const Params& P, int64_t ncols_total, bool sign, hipStr
     if (ev_tree && (e = hipEventRecord(ev_tree[0], s)) != hipSuccess) return e;
     if ((e = launch_tree(P, s)) != hipSuccess) return e;
     if (ev_tree && (e = hipEventRecord(ev_tree[1], s)) != hipSuccess) return e;
+    if ((e = launch_check(P, s)) != hipSuccess) return e;
     if ((e = launch_finalize(P, s)) != hipSuccess) return e;
     if (sign && P.jobz && (e = launch_sign(P, ncols_total, s)) != hipSuccess) return e;
     return hipSuccess;

@@ -89,7 +89,22 @@ struct Node {
     double sigma;     // accumulated shift: lambda(T) = sigma + lambda(node)
     double lgap, rgap;  // absolute gaps to the neighbours outside [a, b]
     double spdiam;    // spectral diameter of the block's root
-    double pad;
+    double checked;   // nonzero: the columns of this node or of an ancestor
+                      // are checked for orthogonality after the tree
+};
+
+// Columns of a cluster whose representation passed no element-growth test
+// (Alg. 3.8, last resort), checked for orthogonality after the tree and
+// re-orthogonalised when it is lost (remark (6) on the shift selection of
+// Sec. 3.2.3: check the accuracy of the cluster's eigenpairs).
+constexpr int kCheckMax = 64;   // widest cluster that is checked (columns)
+struct CheckRec {
+    int64_t z;        // offset in Z of the first column, at the block's first row
+    int64_t ldz;
+    int64_t n;        // rows of the block
+    int64_t m;        // columns, 2..kCheckMax
+    double loss[2];   // max |Z^T Z - I| found by the two passes (written on the device)
+    int64_t pad[2];
 };
 
 // Words that many workers hit (queue heads and tails, the pending count, the
@@ -115,6 +130,8 @@ struct Ctl {
     int64_t qd_steps, n_tasks, n_single, n_rqi, n_blocks;
     int64_t trace_top;
     int64_t n_sturm;
+    int64_t chk_top;      // records in Params::chk
+    int64_t n_checked, n_repaired, n_check_failed;
 #ifdef __HIPCC__
     __device__ __host__ uint64_t* head(int q) { return head_ + q * kLineU64; }
     __device__ __host__ uint64_t* tail(int q) { return tail_ + q * kLineU64; }
@@ -166,6 +183,8 @@ struct Params {
     uint64_t timeout_ticks;
     TraceRec* trace;
     int64_t trace_cap;
+    CheckRec* chk;        // clusters checked after the tree (see CheckRec)
+    int64_t chk_cap;
 };
 
 }  // namespace mrrr

@@ -2453,7 +2453,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         nd.lgap = __builtin_inf();
         nd.rgap = __builtin_inf();
         nd.spdiam = spdiam;
-        nd.pad = 0.0;
+        nd.checked = 0.0;
         P.nodes[id] = nd;
         P.blocks[bid].root = id;
     }
@@ -2692,6 +2692,31 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     const int id = new_node(P);
     if (id < 0) return;
     if (l == 0) {
+        // an unverified representation's columns are checked after the tree,
+        // unless an ancestor's check already covers them
+        double checked = par.checked;
+        if (unverified && checked == 0.0 && P.jobz) {
+            const int c0 = max(p, blk.w0), c1 = min(q, blk.w1);
+            const int64_t m = (int64_t)c1 - c0 + 1;
+            if (m >= 2 && m <= kCheckMax) {
+                const int64_t k = __hip_atomic_fetch_add(&P.ctl->chk_top, (int64_t)1, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                if (k < P.chk_cap) {
+                    const Problem pr = P.probs[blk.prob];
+                    CheckRec rc;
+                    rc.z = pr.zoff + (blk.col0 + (c0 - blk.w0)) * pr.ldz + (blk.row0 - pr.row0);
+                    rc.ldz = pr.ldz;
+                    rc.n = n;
+                    rc.m = m;
+                    rc.loss[0] = rc.loss[1] = 0.0;
+                    rc.pad[0] = rc.pad[1] = 0;
+                    P.chk[k] = rc;
+                    checked = 1.0;
+                } else {
+                    add_stat(&P.ctl->n_check_failed, 1);
+                }
+            }
+        }
         Node nd;
         nd.data = off;
         nd.block = par.block;
@@ -2704,7 +2729,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         nd.lgap = lgap;
         nd.rgap = rgap;
         nd.spdiam = spd;
-        nd.pad = 0.0;
+        nd.checked = checked;
         P.nodes[id] = nd;
     }
     // 3. child brackets: (lambda(1 -+ nu) - tau)(1 -+ nu), nu = 10 k_rr n eps
