@@ -7,7 +7,7 @@ from oracle import metrics as M
 
 pytestmark = pytest.mark.gpu
 
-from _gpu_util import EPS, check_pairs, to_dev  # noqa: E402
+from _gpu_util import EPS, check_pairs, gpu_residual_orth, to_dev  # noqa: E402
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -63,6 +63,37 @@ def test_batched_with_splits_and_families(orc):
     for d, e, w, Z in _split_batch(sizes, off, d_cat, e_cat, w_cat.cpu().numpy(), Z_cat.cpu().numpy()):
         wo, Zo = orc.solve(d, e)
         check_pairs(d, e, w, Z, wo, Zo)
+
+
+def test_batched_glued_unverified_clusters_checked(orc):
+    """The check of unverified clusters inside the captured graph: glued
+    Wilkinson with 400 and 300 blocks in one batch (orthogonality 235 and
+    137 n eps without the check), residual and orthogonality of all pairs
+    of each, sampled eigenvalues against the oracle, and a replay of the
+    graph bitwise equal to the first run."""
+    import torch
+    import paper_1401_4950_amd as mr
+    mats = [ti.glued_wilkinson(8400), ti.glued_wilkinson(6300)]
+    sizes = [len(d) for d, _ in mats]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    d_cat = np.concatenate([d for d, _ in mats])
+    e_cat = np.concatenate([np.concatenate([e, [0.0]]) for _, e in mats])
+    w_cat, Z_cat = mr.eigh_tridiagonal_batched(to_dev(d_cat), to_dev(e_cat), off)
+    torch.cuda.synchronize()
+    zo = 0
+    for (d, e), nb, r0 in zip(mats, sizes, off[:-1]):
+        w = w_cat[r0:r0 + nb]
+        Z = Z_cat[zo:zo + nb * nb].reshape(nb, nb).T
+        zo += nb * nb
+        idx = np.unique(np.linspace(1, nb, 12).astype(int))
+        wo = np.array([orc.eigval_index(d, e, int(k)) for k in idx])
+        tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, nb)))
+        assert np.max(np.abs(w.cpu().numpy()[idx - 1] - wo)) <= 4 * nb * EPS * tn
+        res, orth = gpu_residual_orth(d, e, w, Z, tn)
+        assert res <= 10 and orth <= 100, (nb, res, orth)
+    w2, Z2 = mr.eigh_tridiagonal_batched(to_dev(d_cat), to_dev(e_cat), off)
+    torch.cuda.synchronize()
+    assert torch.equal(w_cat, w2) and torch.equal(Z_cat, Z2)
 
 
 def test_batched_config4_sampled(orc):
