@@ -85,6 +85,11 @@ typedef struct {
                                 b, tune[3b..3b+2] = lanes_per_eig, bundle,
                                 slice_max (an entry <= 0 keeps the value
                                 above); read during the call only */
+    double check_tol;        /* columns of a cluster whose representation
+                                passed no growth test are corrected when
+                                max |Z^T Z - I| over them exceeds
+                                check_tol * n * eps (20); 0 corrects every
+                                checked cluster */
 } mrrr_options_t;
 
 /* One record per executed device task (the per-task timeline of the

@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
         ("timeout_s", ctypes.c_double), ("arena_scale", ctypes.c_double),
         ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int64),
         ("lanes_per_eig", ctypes.c_int32), ("bundle", ctypes.c_int32),
-        ("tune", ctypes.c_void_p),
+        ("tune", ctypes.c_void_p), ("check_tol", ctypes.c_double),
     ]
 
 

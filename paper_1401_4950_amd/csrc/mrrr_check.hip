@@ -10,7 +10,8 @@
 // most kCheckMax wanted columns (the outermost one of a subtree); after the
 // tree, one workgroup per record forms the Gram matrix G = Z_c^T Z_c of those
 // columns (mrrr_check_small_kernel: up to kSmallM columns by plain FMAs;
-// mrrr_check_wide_kernel: wider clusters on the matrix cores); where max |G - I| exceeds kCheckTol n eps,
+// mrrr_check_wide_kernel: wider clusters on the matrix cores); where
+// max |G - I| exceeds check_tol n eps (an option, 20 by default),
 // mrrr_repair_kernel replaces Z_c by the first-order symmetric (Loewdin)
 // orthogonalisation Z_c (I - E / 2), E = G - I, twice: the columns move as
 // little as possible, and after the second pass the loss is of the order of
@@ -36,7 +37,6 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kGroups = kCheckMax / 16;                   // 16-column groups
 constexpr int kPairs = kGroups * (kGroups + 1) / 2;       // Gram blocks gi <= gj
 constexpr double kEpsC = 1.1102230246251565e-16;          // 2^-53
-constexpr double kCheckTol = 20.0;    // repair when max |G - I| > kCheckTol n eps
 constexpr double kRepairMax = 1e-3;   // m max |G - I| above this: not repaired
 constexpr int kEStride = kCheckMax + 1;
 
@@ -44,7 +44,9 @@ __device__ __forceinline__ void stat_add(int64_t* p, int64_t v) {
     if (v) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ double check_threshold(int64_t n) { return kCheckTol * (double)n * kEpsC; }
+__device__ __forceinline__ double check_threshold(const Params& P, int64_t n) {
+    return P.check_tol * (double)n * kEpsC;
+}
 
 // Gram blocks (gi, gj), gi <= gj < TT, of the m columns at Z (stride ldz)
 // over rows [b, e) by one wavefront, 4 U rows per step: lane (c, k) loads
@@ -230,7 +232,7 @@ __device__ __forceinline__ void check_done(const Params& P, int64_t rec, const C
     if (threadIdx.x == 0) {
         P.chk[rec].loss[0] = loss;
         stat_add(&P.ctl->n_checked, 1);
-        const bool failed = loss > check_threshold(rc.n) && !((double)rc.m * loss <= kRepairMax);
+        const bool failed = loss > check_threshold(P, rc.n) && !((double)rc.m * loss <= kRepairMax);
         stat_add(&P.ctl->n_check_failed, failed ? 1 : 0);
     }
 }
@@ -290,7 +292,7 @@ extern "C" __global__ __launch_bounds__(kRepThreads) void mrrr_repair_kernel(Par
         const int m = (int)rc.m;
         const int64_t n = rc.n, ldz = rc.ldz;
         const double loss0 = rc.loss[0];
-        if (!(loss0 > check_threshold(n)) || !((double)m * loss0 <= kRepairMax)) continue;
+        if (!(loss0 > check_threshold(P, n)) || !((double)m * loss0 <= kRepairMax)) continue;
         double* Z = P.Z + rc.z;
         for (int pass = 0; pass < 2; ++pass) {
             __syncthreads();   // the previous E is no longer read

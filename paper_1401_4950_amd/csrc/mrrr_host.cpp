@@ -126,6 +126,7 @@ extern "C" void mrrr_default_options(mrrr_options_t* o) {
     o->tune = nullptr;
     o->timeout_s = 30.0;
     o->arena_scale = 1.0;
+    o->check_tol = 20.0;
 }
 
 extern "C" const char* mrrr_status_string(int s) {
@@ -282,6 +283,7 @@ void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int worker
     P.timeout_ticks = (uint64_t)std::max(1.0, o.timeout_s * wall_khz * 1000.0);
     P.trace = (o.trace && o.trace_cap > 0) ? static_cast<TraceRec*>(o.trace) : nullptr;
     P.trace_cap = P.trace ? o.trace_cap : 0;
+    P.check_tol = o.check_tol;
 }
 
 int check_options(const mrrr_options_t& o) {
@@ -293,6 +295,7 @@ int check_options(const mrrr_options_t& o) {
     if (o.trace_cap < 0) return 1;
     if (o.lanes_per_eig < 1 || o.lanes_per_eig > kWave || (o.lanes_per_eig & (o.lanes_per_eig - 1))) return 1;
     if (o.bundle < 1 || o.bundle > kWave) return 1;
+    if (!(o.check_tol >= 0.0 && o.check_tol <= 1e15)) return 1;
     return 0;
 }
 

@@ -185,6 +185,7 @@ struct Params {
     int64_t trace_cap;
     CheckRec* chk;        // clusters checked after the tree (see CheckRec)
     int64_t chk_cap;
+    double check_tol;     // correct when max |Z^T Z - I| > check_tol n eps
 };
 
 }  // namespace mrrr

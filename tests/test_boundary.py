@@ -34,6 +34,7 @@ def test_defaults_and_status_strings(lib):
     assert o.gaptol == 1e-3 and o.rtol_class == 1e-5
     assert o.perturb_xi == 8.0 and o.max_rqi == 10 and o.max_shift_tries == 16
     assert o.lanes_per_eig == 64 and o.bundle == 64 and not o.tune
+    assert o.check_tol == 20.0   # the last field: the ctypes mirror has the header's layout
     for code in range(0, 8):
         assert lib.mrrr_status_string(code)
     assert b"invalid" in lib.mrrr_status_string(-3)

@@ -250,6 +250,75 @@ def test_glued_wilkinson_unverified_clusters_checked(orc, n):
     assert res <= 10 and orth <= 100, (res, orth)
 
 
+def test_checked_cluster_cut_by_an_index_range(orc):
+    """An index range that cuts through the glued Wilkinson (n = 8400)
+    cluster whose columns the check corrects: only the wanted columns are
+    checked (and corrected), at the right place in Z."""
+    import torch
+    import paper_1401_4950_amd as mr
+    n = 8400
+    d, e = ti.family("glued_wilkinson", n, 0)
+    il, iu = 7990, 8020
+    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e), select="i", select_range=(il, iu))
+    torch.cuda.synchronize()
+    st = mr.last_stats()
+    assert st["n_checked"] >= 1 and st["n_check_failed"] == 0, st
+    wo = np.array([orc.eigval_index(d, e, k) for k in range(il, iu + 1)])
+    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
+    wh, Zh = w.cpu().numpy(), Z.cpu().numpy()
+    assert np.max(np.abs(wh - wo)) <= 4 * n * EPS * tn
+    r, o = M.scaled(d, e, wh, Zh, tn)
+    assert r <= 10 and o <= 100, (r, o)
+
+
+def test_checked_clusters_in_a_split_matrix(orc):
+    """Two glued Wilkinson blocks of 8400 rows with a zero coupling: the
+    second block's checked columns sit 8400 rows down, and the final merge
+    interleaves the two blocks' columns after any correction.  With
+    check_tol = 0 every checked cluster is corrected, which must keep the
+    residual and orthogonality bounds."""
+    import torch
+    import paper_1401_4950_amd as mr
+    d1, e1 = ti.family("glued_wilkinson", 8400, 0)
+    d = np.concatenate([d1, d1])
+    e = np.concatenate([e1, [0.0], e1])
+    n = len(d)
+    idx = np.unique(np.linspace(1, n, 16).astype(int))
+    wo = np.array([orc.eigval_index(d, e, int(k)) for k in idx])
+    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
+    for opts in (None, {"check_tol": 0.0}):
+        w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e), options=opts)
+        torch.cuda.synchronize()
+        st = mr.last_stats()
+        assert st["n_blocks"] == 2 and st["n_checked"] >= 2 and st["n_check_failed"] == 0, st
+        if opts:
+            assert st["n_reorthogonalized"] >= 2, st
+        assert np.max(np.abs(w.cpu().numpy()[idx - 1] - wo)) <= 4 * n * EPS * tn
+        res, orth = gpu_residual_orth(d, e, w, Z, tn)
+        assert res <= 10 and orth <= 100, (opts, res, orth)
+        del Z
+
+
+@pytest.mark.parametrize("fam,n", [("random", 6000), ("glued_wilkinson", 4200)])
+def test_every_checked_cluster_corrected(orc, fam, n):
+    """check_tol = 0 corrects every checked cluster (hundreds, of 2 to 64
+    columns): the correction itself must keep the eigenpairs within the
+    bounds, reproducibly."""
+    import torch
+    import paper_1401_4950_amd as mr
+    d, e = ti.family(fam, n, 0)
+    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e), options={"check_tol": 0.0})
+    torch.cuda.synchronize()
+    st = mr.last_stats()
+    assert st["n_checked"] >= 20 and st["n_reorthogonalized"] >= 20 and st["n_check_failed"] == 0, st
+    w2, Z2 = mr.eigh_tridiagonal(to_dev(d), to_dev(e), options={"check_tol": 0.0})
+    torch.cuda.synchronize()
+    assert torch.equal(w, w2) and torch.equal(Z, Z2)
+    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
+    res, orth = gpu_residual_orth(d, e, w, Z, tn)
+    assert res <= 10 and orth <= 100, (res, orth)
+
+
 def test_index_range_on_a_long_matrix(orc):
     """An index range inside 1-2-1's large cluster at n = 6000 (the cluster
     tree and the shared end refinement run as for the whole spectrum)
