@@ -195,12 +195,13 @@ __device__ __forceinline__ void blocks_from_lds(dbl4 (&acc)[kPairs], const doubl
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[p][r] += slot[(p * 4 + r) * 64 + lane];
 }
-__device__ double wide_loss(const double* Z, int64_t ldz, int64_t n, int m, double* red) {
+// The blocks of all n rows by the four waves of a workgroup; the sums end in
+// wave 0's acc.
+__device__ void gram4(const double* Z, int64_t ldz, int64_t n, int m, double* red, dbl4 (&acc)[kPairs]) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t q = (n + 3) / 4;
     const int64_t b = (int64_t)wave * q < n ? (int64_t)wave * q : n;
     const int64_t e = (b + q < n) ? b + q : n;
-    dbl4 acc[kPairs];
     gram(Z, ldz, b, e, m, acc);
     constexpr int kSlot = kPairs * 4 * 64;
     if (wave >= 2) blocks_to_lds(acc, red + (wave - 2) * kSlot, lane);
@@ -209,11 +210,14 @@ __device__ double wide_loss(const double* Z, int64_t ldz, int64_t n, int m, doub
     __syncthreads();
     if (wave == 1) blocks_to_lds(acc, red, lane);
     __syncthreads();
+    if (wave == 0) blocks_from_lds(acc, red, lane);
+}
+
+__device__ double wide_loss(const double* Z, int64_t ldz, int64_t n, int m, double* red) {
+    dbl4 acc[kPairs];
+    gram4(Z, ldz, n, m, red, acc);
     double lm = 0.0;
-    if (wave == 0) {
-        blocks_from_lds(acc, red, lane);
-        lm = gram_loss(acc, m);
-    }
+    if ((threadIdx.x >> 6) == 0) lm = gram_loss(acc, m);
     return lm;   // valid in wave 0
 }
 
@@ -277,13 +281,68 @@ void mrrr_check_wide_kernel(Params P) {
     }
 }
 
+constexpr int kRepThreads = 256;
+
+// Z_c <- Z_c (I - E / 2) for m <= KM columns, one row per thread: the row
+// is copied into registers first; x_j is read again from memory (a register
+// array cannot be indexed by j), one column ahead of its use, and so is
+// column j + 1 of E (for KM <= 32, where the registers allow it).
+template <int KM>
+__device__ void apply_rows(double* __restrict__ Z, int64_t ldz, int64_t n, int m, const double* E) {
+    for (int64_t row = threadIdx.x; row < n; row += kRepThreads) {
+        double x[KM];
+#pragma unroll
+        for (int i = 0; i < KM; ++i) x[i] = (i < m) ? Z[(int64_t)i * ldz + row] : 0.0;
+        double xn = Z[row];
+        if constexpr (KM <= 32) {
+            double ec[KM];
+#pragma unroll
+            for (int i = 0; i < KM; ++i) ec[i] = E[i * kEStride];
+            for (int j = 0; j < m; ++j) {
+                const double xj = xn;
+                const int jn = (j + 1 < m) ? j + 1 : j;
+                xn = Z[(int64_t)jn * ldz + row];
+                double en[KM];
+#pragma unroll
+                for (int i = 0; i < KM; ++i) en[i] = E[i * kEStride + jn];
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+                for (int i = 0; i < KM; i += 4) {
+                    s0 = fma(ec[i + 0], x[i + 0], s0);
+                    s1 = fma(ec[i + 1], x[i + 1], s1);
+                    s2 = fma(ec[i + 2], x[i + 2], s2);
+                    s3 = fma(ec[i + 3], x[i + 3], s3);
+                }
+                Z[(int64_t)j * ldz + row] = fma(-0.5, (s0 + s1) + (s2 + s3), xj);
+#pragma unroll
+                for (int i = 0; i < KM; ++i) ec[i] = en[i];
+            }
+        } else {
+            for (int j = 0; j < m; ++j) {
+                const double xj = xn;
+                if (j + 1 < m) xn = Z[(int64_t)(j + 1) * ldz + row];
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+                for (int i = 0; i < KM; i += 4) {
+                    s0 = fma(E[(i + 0) * kEStride + j], x[i + 0], s0);
+                    s1 = fma(E[(i + 1) * kEStride + j], x[i + 1], s1);
+                    s2 = fma(E[(i + 2) * kEStride + j], x[i + 2], s2);
+                    s3 = fma(E[(i + 3) * kEStride + j], x[i + 3], s3);
+                }
+                Z[(int64_t)j * ldz + row] = fma(-0.5, (s0 + s1) + (s2 + s3), xj);
+            }
+        }
+    }
+}
+
 // One workgroup per record whose loss exceeds the tolerance (and is small
 // enough to correct): Z_c <- Z_c (I - E / 2) twice, the second time with the
-// E of the corrected columns.  Wave 0 forms E and stages it in LDS; every
-// thread then owns rows of Z_c and rewrites them from a copy in registers.
-constexpr int kRepThreads = 256;
+// E of the corrected columns.  The four waves form the Gram blocks, wave 0
+// stages E in LDS; every thread then owns rows of Z_c and rewrites them from
+// a copy in registers.
 extern "C" __global__ __launch_bounds__(kRepThreads) void mrrr_repair_kernel(Params P) {
     __shared__ double E[kCheckMax * kEStride];
+    __shared__ double red[kRedWords];
     const int tid = threadIdx.x;
     int64_t nrec = P.ctl->chk_top;
     if (nrec > P.chk_cap) nrec = P.chk_cap;
@@ -298,9 +357,9 @@ extern "C" __global__ __launch_bounds__(kRepThreads) void mrrr_repair_kernel(Par
             __syncthreads();   // the previous E is no longer read
             for (int idx = tid; idx < kCheckMax * kEStride; idx += kRepThreads) E[idx] = 0.0;
             __syncthreads();
+            dbl4 acc[kPairs];
+            gram4(Z, ldz, n, m, red, acc);
             if (tid < 64) {
-                dbl4 acc[kPairs];
-                gram(Z, ldz, 0, n, m, acc);
                 if (pass == 1) {
                     const double loss1 = gram_loss(acc, m);
                     if (tid == 0) P.chk[rec].loss[1] = loss1;
@@ -313,23 +372,11 @@ extern "C" __global__ __launch_bounds__(kRepThreads) void mrrr_repair_kernel(Par
                 });
             }
             __syncthreads();
-            for (int64_t row = tid; row < n; row += kRepThreads) {
-                double x[kCheckMax];
-#pragma unroll
-                for (int i = 0; i < kCheckMax; ++i) x[i] = (i < m) ? Z[(int64_t)i * ldz + row] : 0.0;
-                for (int j = 0; j < m; ++j) {
-                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-                    for (int i = 0; i < kCheckMax; i += 4) {
-                        s0 = fma(E[(i + 0) * kEStride + j], x[i + 0], s0);
-                        s1 = fma(E[(i + 1) * kEStride + j], x[i + 1], s1);
-                        s2 = fma(E[(i + 2) * kEStride + j], x[i + 2], s2);
-                        s3 = fma(E[(i + 3) * kEStride + j], x[i + 3], s3);
-                    }
-                    const double sj = (s0 + s1) + (s2 + s3);
-                    double* zj = Z + (int64_t)j * ldz + row;
-                    *zj = fma(-0.5, sj, *zj);
-                }
+            switch ((m + 15) >> 4) {
+                case 1: apply_rows<16>(Z, ldz, n, m, E); break;
+                case 2: apply_rows<32>(Z, ldz, n, m, E); break;
+                case 3: apply_rows<48>(Z, ldz, n, m, E); break;
+                default: apply_rows<64>(Z, ldz, n, m, E); break;
             }
         }
         if (tid == 0) stat_add(&P.ctl->n_repaired, 1);
