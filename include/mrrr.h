@@ -40,10 +40,13 @@ typedef struct mrrr_batched_plan_s *mrrr_batched_plan_t;
 typedef enum {
     MRRR_OK = 0,
     /* A new representation was accepted although its element growth was
-     * above the threshold (Alg. 3.8, last line: "return the one with the
-     * smallest element growth"), or a cluster hit the depth limit.  Outputs
-     * are filled; stats->n_unverified_rrr says how often.  "Code may fail but
-     * should never lie" (Sec. 3.2.3). */
+     * above the threshold (Alg. 3.8 keeps the candidate of least growth when
+     * none passes), or a cluster hit the depth limit.  Outputs are filled;
+     * stats->n_unverified_rrr says how often, and the columns of such
+     * clusters are checked for orthogonality (and corrected when needed)
+     * after the tree, with stats->n_check_failed counting the ones that could
+     * not be.  The status reports the untested acceptance instead of hiding
+     * it (Sec. 3.2.3, remark (6) on the shift selection). */
     MRRR_WARN_UNVERIFIED = 1,
     MRRR_ENOMEM = 2,     /* device allocation or a work-queue capacity failed */
     MRRR_ENOCONV = 3,    /* an eigenvalue failed to converge */
@@ -180,10 +183,10 @@ const char *mrrr_status_string(int status);
  *   stats    host, may be NULL.  When non-NULL the call synchronises and
  *            fills it.
  * The call always waits for the device to finish (it must read back the
- * device status word to honour "never lie").  Errors: negative argument
- * index, MRRR_ENOMEM, MRRR_ETIMEOUT, MRRR_ENOTIMPL (INDEX range on a matrix
- * that splits into several blocks), MRRR_EHIP.  MRRR_WARN_UNVERIFIED still
- * fills all outputs. */
+ * device status word, so that a failure is reported, never hidden).
+ * Errors: negative argument index, MRRR_ENOMEM, MRRR_ETIMEOUT,
+ * MRRR_ENOTIMPL (INDEX range on a matrix that splits into several blocks),
+ * MRRR_EHIP.  MRRR_WARN_UNVERIFIED still fills all outputs. */
 int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double *d, const double *e,
                 int range, double vl, double vu, int64_t il, int64_t iu,
                 const mrrr_options_t *opts, int64_t *m, double *w, double *Z,
