@@ -5,9 +5,9 @@
  *
  * What it computes is the plain definition of the result: the wanted
  * eigenvalues of T = tridiag(e, d, e) in ascending order and orthonormal
- * eigenvectors with small residuals.  It gets there the slow, obvious way the
- * thesis describes as "bisection and inverse iteration" (Sec. 2.2, method BI;
- * the LAPACK pair DSTEBZ/DSTEIN):
+ * eigenvectors with small residuals.  It gets there the slow, obvious way:
+ * bisection followed by inverse iteration (Sec. 2.2, method BI; the LAPACK
+ * pair DSTEBZ/DSTEIN):
  *
  *   1. Gershgorin interval (App. B, Alg. B.3), with |beta_1| in the first row.
  *   2. Splitting where |e_i| <= eps*sqrt(n)*bnorm (Sec. 3.2.1, eq. tolsplit).
@@ -283,7 +283,8 @@ static void orc_sign_fix(int64_t n, double *x)
 }
 
 /* Gram-Schmidt of x against columns Q[:, 0..m) (each length n, ld = ldq),
- * applied twice ("twice is enough"); inner products in parallel when big. */
+ * applied twice (a second sweep restores what rounding lost in the first);
+ * inner products in parallel when big. */
 static void orc_gs(int64_t n, double *x, const double *Q, int64_t ldq, int64_t m,
                    int par)
 {

@@ -131,7 +131,7 @@ DEV int wave_or(int x) {
 }
 
 // splitmix64 (Steele, Lea and Flood, 2014): a counter-based generator for the
-// "random" relative perturbation of the root (Alg. 3.2, line 2).
+// pseudo-random relative perturbation of the root (Alg. 3.2).
 DEV uint64_t splitmix64(uint64_t x) {
     x += 0x9E3779B97F4A7C15ull;
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -1733,8 +1733,8 @@ DEV int new_node(const Params& P) {   // all lanes get the id
 
 // ------------------------------------- cooperative refinement
 //
-// The refinement of a cluster's end eigenvalues to full accuracy (Alg. 3.8,
-// line 1) lies on the critical path of a deep cluster tree while most
+// The refinement of a cluster's end eigenvalues to full accuracy (the first
+// step of Alg. 3.8) lies on the critical path of a deep cluster tree while most
 // workers are idle.  The worker that owns it (the leader) then lends its
 // passes to idle workers without changing them: the leader counts one pass
 // of the sequential multisection schedule (the one refine_members follows:
@@ -2412,8 +2412,8 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     __syncthreads();   // the rows other lanes wrote are read below
     double* Dr = C0;
     double* Lr = Dr + n;
-    // "random" relative perturbation of every datum by at most xi*eps
-    // (Alg. 3.2, line 2)
+    // pseudo-random relative perturbation of every datum by at most xi*eps
+    // (Alg. 3.2)
     const double amp = P.xi * kEps;
     for (int64_t i = l; i < n; i += kWave) {
         const uint64_t g = (uint64_t)(blk.row0 + i);
@@ -2574,7 +2574,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     double* Cn = P.arena + off;
     double* cks = Cn + 2 * n;
     const int64_t cboff = off + 3 * n + 64;   // kCbWords <= n + 64 words are left for n >= kCoopMinRows
-    // 1. the cluster's end eigenvalues to full accuracy (Alg. 3.8, line 1)
+    // 1. the cluster's end eigenvalues to full accuracy (Alg. 3.8, first step)
     if (l < 2) {
         const int j = (l == 0) ? p : q;
         const int64_t slot = sb + j;
@@ -2679,7 +2679,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
             set_error(P, kErrNoConv);
             return;
         }
-        // no candidate passed: the least element growth (Alg. 3.8, last line)
+        // no candidate passed: the least element growth (Alg. 3.8, last resort)
         chosen = best_lane;
         tau = best_tau;
         chosen_growth = best;
