@@ -244,7 +244,8 @@ __device__ __forceinline__ void check_done(const Params& P, int64_t rec, const C
 extern "C" __global__ __launch_bounds__(kChkThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void mrrr_check_small_kernel(Params P) {
     __shared__ double red[4 * kSmallM * (kSmallM + 1) / 2];
-    int64_t nrec = P.ctl->chk_top;
+    // after a failed tree (the host retries or reports it) Z is incomplete
+    int64_t nrec = (P.ctl->error == kErrNone) ? P.ctl->chk_top : 0;
     if (nrec > P.chk_cap) nrec = P.chk_cap;
     for (int64_t rec = blockIdx.x; rec < nrec; rec += gridDim.x) {
         const CheckRec rc = P.chk[rec];
@@ -269,7 +270,8 @@ void mrrr_check_small_kernel(Params P) {
 extern "C" __global__ __launch_bounds__(kChkThreads) __attribute__((amdgpu_waves_per_eu(2)))
 void mrrr_check_wide_kernel(Params P) {
     __shared__ double red[kRedWords];
-    int64_t nrec = P.ctl->chk_top;
+    // after a failed tree (the host retries or reports it) Z is incomplete
+    int64_t nrec = (P.ctl->error == kErrNone) ? P.ctl->chk_top : 0;
     if (nrec > P.chk_cap) nrec = P.chk_cap;
     for (int64_t rec = blockIdx.x; rec < nrec; rec += gridDim.x) {
         const CheckRec rc = P.chk[rec];
@@ -344,7 +346,8 @@ extern "C" __global__ __launch_bounds__(kRepThreads) void mrrr_repair_kernel(Par
     __shared__ double E[kCheckMax * kEStride];
     __shared__ double red[kRedWords];
     const int tid = threadIdx.x;
-    int64_t nrec = P.ctl->chk_top;
+    // after a failed tree (the host retries or reports it) Z is incomplete
+    int64_t nrec = (P.ctl->error == kErrNone) ? P.ctl->chk_top : 0;
     if (nrec > P.chk_cap) nrec = P.chk_cap;
     for (int64_t rec = blockIdx.x; rec < nrec; rec += gridDim.x) {
         const CheckRec rc = P.chk[rec];
