@@ -3308,11 +3308,21 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_sign_kernel(Params P, int6
         const int64_t col = g - pr.row0;
         if (col >= pr.m) continue;
         double* z = P.Z + pr.zoff + col * pr.ldz;
+        // each lane visits its rows l, l + 64, ... in increasing order (so a
+        // later equal entry never wins), eight loads in flight
+        constexpr int U = 8;
         double best = -1.0;
         int64_t bi = 0;
-        for (int64_t i = l; i < pr.n; i += kWave) {
-            const double v = fabs(z[i]);
-            if (v > best) { best = v; bi = i; }
+        for (int64_t i0 = l; i0 < pr.n; i0 += (int64_t)kWave * U) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + (int64_t)u * kWave;
+                v[u] = (i < pr.n) ? fabs(z[i]) : -1.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (v[u] > best) { best = v[u]; bi = i0 + (int64_t)u * kWave; }
         }
         for (int o = 32; o > 0; o >>= 1) {
             const double ob = __shfl_xor(best, o);
@@ -3320,8 +3330,21 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_sign_kernel(Params P, int6
             if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
         const bool neg = z[bi] < 0.0;
-        if (neg)
-            for (int64_t i = l; i < pr.n; i += kWave) z[i] = -z[i];
+        if (neg) {
+            for (int64_t i0 = l; i0 < pr.n; i0 += (int64_t)kWave * U) {
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t i = i0 + (int64_t)u * kWave;
+                    v[u] = (i < pr.n) ? z[i] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t i = i0 + (int64_t)u * kWave;
+                    if (i < pr.n) z[i] = -v[u];
+                }
+            }
+        }
     }
 }
 
