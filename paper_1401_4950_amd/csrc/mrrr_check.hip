@@ -44,6 +44,12 @@ __device__ __forceinline__ void stat_add(int64_t* p, int64_t v) {
     if (v) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// |G_ij - delta_ij|, with a NaN counted as infinite
+__device__ __forceinline__ double loss_term(double g, bool diag) {
+    const double a = fabs(g - (diag ? 1.0 : 0.0));
+    return (a <= 1e300) ? a : __builtin_inf();
+}
+
 __device__ __forceinline__ double check_threshold(const Params& P, int64_t n) {
     return P.check_tol * (double)n * kEpsC;
 }
@@ -112,11 +118,7 @@ __device__ __forceinline__ void for_upper(const dbl4 (&acc)[kPairs], int m, F f)
 // max |G - I| over the wavefront (a NaN counts as infinite)
 __device__ double gram_loss(const dbl4 (&acc)[kPairs], int m) {
     double lm = 0.0;
-    for_upper(acc, m, [&](int i, int j, double g) {
-        double a = fabs(g - (i == j ? 1.0 : 0.0));
-        if (!(a <= 1e300)) a = __builtin_inf();
-        lm = fmax(lm, a);
-    });
+    for_upper(acc, m, [&](int i, int j, double g) { lm = fmax(lm, loss_term(g, i == j)); });
     for (int o = 32; o > 0; o >>= 1) lm = fmax(lm, __shfl_xor(lm, o));
     return lm;
 }
@@ -124,10 +126,6 @@ __device__ double gram_loss(const dbl4 (&acc)[kPairs], int m) {
 constexpr int kChkThreads = 256;                          // 4 waves per record
 constexpr int kSmallM = 8;
 constexpr int kRedWords = 2 * kPairs * 4 * 64;            // two waves' blocks
-__device__ __forceinline__ double loss_term(double g, bool diag) {
-    double a = fabs(g - (diag ? 1.0 : 0.0));
-    return (a <= 1e300) ? a : __builtin_inf();
-}
 
 // max |G - I| of M <= kSmallM columns by plain FMAs: thread t takes rows
 // t, t + 256, ... (coalesced), the M (M + 1) / 2 sums stay in registers,
