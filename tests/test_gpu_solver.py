@@ -319,6 +319,22 @@ def test_every_checked_cluster_corrected(orc, fam, n):
     assert res <= 10 and orth <= 100, (res, orth)
 
 
+def test_check_tol_option_edges():
+    """check_tol < 0 is an invalid option (argument 10 of mrrr_dstemr); a
+    huge check_tol still checks the recorded clusters but corrects none."""
+    import torch
+    import paper_1401_4950_amd as mr
+    from paper_1401_4950_amd import MrrrError
+    d, e = ti.family("glued_wilkinson", 4200, 0)
+    with pytest.raises(MrrrError) as ex:
+        mr.eigh_tridiagonal(to_dev(d), to_dev(e), options={"check_tol": -1.0})
+    assert ex.value.code == -10
+    mr.eigh_tridiagonal(to_dev(d), to_dev(e), options={"check_tol": 1e15})
+    torch.cuda.synchronize()
+    st = mr.last_stats()
+    assert st["n_checked"] > 0 and st["n_reorthogonalized"] == 0, st
+
+
 def test_index_range_on_a_long_matrix(orc):
     """An index range inside 1-2-1's large cluster at n = 6000 (the cluster
     tree and the shared end refinement run as for the whole spectrum)
