@@ -3045,19 +3045,34 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
     }
     const double* d = P.d + pr->row0;
     const double* e = P.e + pr->row0;
+    // Gershgorin interval and the finiteness test in one sweep, four rows
+    // per lane in flight (min and max do not depend on the order)
+    constexpr int U = 4;
     double gl = __builtin_inf(), gu = -__builtin_inf();
-    for (int64_t i = l; i < n; i += kWave) {
-        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
-        gl = fmin(gl, d[i] - r);
-        gu = fmax(gu, d[i] + r);
+    int bad_d = 0, bad_e = 0;
+    for (int64_t i0 = l; i0 < n; i0 += (int64_t)kWave * U) {
+        double dv[U], ev[U], em[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * kWave;
+            dv[u] = (i < n) ? d[i] : 0.0;
+            ev[u] = (i < n - 1) ? e[i] : 0.0;
+            em[u] = (i > 0 && i < n) ? e[i - 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + (int64_t)u * kWave;
+            if (i < n) {
+                const double r = fabs(em[u]) + fabs(ev[u]);
+                gl = fmin(gl, dv[u] - r);
+                gu = fmax(gu, dv[u] + r);
+                bad_d |= __builtin_isfinite(dv[u]) ? 0 : 1;
+                if (i < n - 1) bad_e |= __builtin_isfinite(ev[u]) ? 0 : 1;
+            }
+        }
     }
     gl = wave_min(gl);
     gu = wave_max(gu);
-    int bad_d = 0, bad_e = 0;
-    for (int64_t i = l; i < n; i += kWave) {
-        bad_d |= __builtin_isfinite(d[i]) ? 0 : 1;
-        if (i < n - 1) bad_e |= __builtin_isfinite(e[i]) ? 0 : 1;
-    }
     if (wave_or(bad_d) || wave_or(bad_e)) {
         if (l == 0) { pr->m = 0; pr->nblocks = 0; }
         set_error(P, wave_or(bad_d) ? kErrBadD : kErrBadE);
@@ -3074,22 +3089,33 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
     Block* B = P.blocks + pr->row0;
     int nb = 0;
     int64_t start = 0;
-    for (int64_t base = 0; base < n - 1; base += kWave) {
-        const int64_t i = base + l;
-        const bool sp = (i < n - 1) && fabs(e[i]) <= tol;
-        uint64_t mk = __ballot(sp);
-        while (mk) {
-            const int t = __ffsll((unsigned long long)mk) - 1;
-            mk &= mk - 1ull;
-            const int64_t is = base + t;
-            if (l == 0) {
-                B[nb].prob = p;
-                B[nb].root = -1;
-                B[nb].row0 = pr->row0 + start;
-                B[nb].n = is - start + 1;
+    // split points in increasing order, four 64-row chunks loaded at once
+    for (int64_t base0 = 0; base0 < n - 1; base0 += (int64_t)kWave * U) {
+        double ev[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base0 + (int64_t)u * kWave + l;
+            ev[u] = (i < n - 1) ? e[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t base = base0 + (int64_t)u * kWave;
+            const int64_t i = base + l;
+            const bool sp = (i < n - 1) && fabs(ev[u]) <= tol;
+            uint64_t mk = __ballot(sp);
+            while (mk) {
+                const int t = __ffsll((unsigned long long)mk) - 1;
+                mk &= mk - 1ull;
+                const int64_t is = base + t;
+                if (l == 0) {
+                    B[nb].prob = p;
+                    B[nb].root = -1;
+                    B[nb].row0 = pr->row0 + start;
+                    B[nb].n = is - start + 1;
+                }
+                ++nb;
+                start = is + 1;
             }
-            ++nb;
-            start = is + 1;
         }
     }
     if (l == 0) {
