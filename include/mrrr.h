@@ -34,7 +34,6 @@ extern "C" {
 #endif
 
 typedef struct mrrr_handle_s *mrrr_handle_t;
-typedef struct mrrr_batched_plan_s *mrrr_batched_plan_t;
 
 /* Status codes (positive).  Negative returns name an invalid argument. */
 typedef enum {
@@ -145,6 +144,10 @@ typedef struct {
                                   max |Z^T Z - I| exceeded 20 n eps */
     int64_t n_check_failed;    /* unverified clusters left unchecked (no record
                                   slot) or too far from orthogonal to correct */
+    int64_t n_check_wide;      /* unverified clusters with more than 64 wanted
+                                  columns: not checked as a whole; those of
+                                  their descendants that are unverified and
+                                  hold at most 64 wanted columns are */
 } mrrr_stats_t;
 
 /* Creates a handle on HIP device `device`.  The handle owns a workspace that
@@ -242,6 +245,21 @@ int mrrr_dstemr_backward_batched(mrrr_handle_t h, int64_t batch,
                                  const double *wbar_cat, const double *Zbar_cat,
                                  double gap_mask_rel, double *dbar_cat,
                                  double *ebar_cat, int64_t *n_masked);
+
+/* Diagnostic: q[i] = a[i] / b[i] by the quotient the kernels use where the
+ * shift selection of Alg. 3.8 and a new representation's rows need
+ * quotients (the hardware reciprocal, one Newton step and Markstein's
+ * residual correction).  For finite, nonzero operands whose IEEE quotient is
+ * finite the result is faithful (one of the two doubles next to the exact
+ * quotient) and equals IEEE division except where the exact quotient lies
+ * within about 2^-70 (relative) of the midpoint between two doubles, since
+ * the reciprocal itself is only accurate to 2^-24.  A zero, infinite or NaN
+ * divisor, an infinite or NaN dividend, and possibly a quotient within about
+ * 2^-24 of overflow, give NaN (the kernels then redo that pass with IEEE
+ * division).  a, b, q: device, n doubles each; enqueued on the handle's
+ * stream, no synchronisation.
+ * Errors: negative argument index, MRRR_EHIP. */
+int mrrr_diag_quotient(mrrr_handle_t h, int64_t n, const double *a, const double *b, double *q);
 
 #ifdef __cplusplus
 }

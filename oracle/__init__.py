@@ -49,12 +49,15 @@ def _load():
         lib.orc_split.restype = i64
         lib.orc_negcount.argtypes = [i64, dp, dp, ctypes.c_double, ctypes.c_double]
         lib.orc_negcount.restype = i64
+        lib.orc_negcount_many.argtypes = [i64, dp, dp, i64, dp, ip]
+        lib.orc_negcount_many.restype = None
         lib.orc_solve.argtypes = [i64, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   i64, i64, dp, dp, i64, ctypes.c_uint64, ctypes.c_double]
         lib.orc_solve.restype = i64
         lib.orc_eigval_index.argtypes = [i64, dp, dp, i64]
         lib.orc_eigval_index.restype = ctypes.c_double
-        lib.orc_eigvec_single.argtypes = [i64, dp, dp, ctypes.c_double, dp, ctypes.c_uint64]
+        lib.orc_sign_fix.argtypes = [i64, dp]
+        lib.orc_sign_fix.restype = None
         lib.orc_jacobi.argtypes = [i64, dp, i64, dp, dp, i64]
         lib.orc_jacobi.restype = ctypes.c_int
         lib.orc_num_threads.restype = ctypes.c_int
@@ -107,6 +110,16 @@ def negcount(d, e, sigma, pivmin=None):
                                     float(sigma), float(pivmin)))
 
 
+def negcounts(d, e, shifts):
+    """Sturm counts of T (App. B, Alg. B.1) at every shift, in parallel."""
+    d, e = _c(d), _c(e)
+    shifts = _c(shifts)
+    out = np.zeros(len(shifts), dtype=np.int64)
+    _load().orc_negcount_many(len(d), _p(d), _p(e if len(e) else np.zeros(1)), len(shifts), _p(shifts),
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return out
+
+
 def solve(d, e, select="all", vl=0.0, vu=0.0, il=1, iu=None, vectors=True,
           seed=0, orfac=1e-3):
     """Eigenpairs of tridiag(e, d, e): (w ascending, Z column-major n x m).
@@ -131,16 +144,16 @@ def solve(d, e, select="all", vl=0.0, vu=0.0, il=1, iu=None, vectors=True,
 
 
 def eigval_index(d, e, k):
-    """k-th smallest eigenvalue (1-based) of an unsplit T, to full accuracy."""
+    """k-th smallest eigenvalue (1-based) of T, to full accuracy: bisection
+    on the Sturm count of T after the same splitting as ``solve``."""
     d, e = _c(d), _c(e)
     return float(_load().orc_eigval_index(len(d), _p(d), _p(e if len(e) else np.zeros(1)), int(k)))
 
 
-def eigvec_single(d, e, lam, seed=0):
-    """Inverse-iteration vector for one well separated eigenvalue."""
-    d, e = _c(d), _c(e)
-    x = np.zeros(len(d))
-    _load().orc_eigvec_single(len(d), _p(d), _p(e if len(e) else np.zeros(1)), float(lam), _p(x), int(seed))
+def sign_fix(x):
+    """The oracle's sign convention applied to a copy of the vector x."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    _load().orc_sign_fix(len(x), _p(x))
     return x
 
 

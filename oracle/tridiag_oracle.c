@@ -126,6 +126,17 @@ int64_t orc_negcount(int64_t n, const double *d, const double *e,
     return count;
 }
 
+/* Alg. B.1 at many shifts: counts[j] = number of eigenvalues of T below
+ * shifts[j], with the pivmin guard of orc_negcount. */
+void orc_negcount_many(int64_t n, const double *d, const double *e,
+                       int64_t nshift, const double *shifts, int64_t *counts)
+{
+    double pivmin = orc_pivmin(n, e);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < nshift; ++j)
+        counts[j] = orc_negcount(n, d, e, shifts[j], pivmin);
+}
+
 /* Alg. 3.3 (bisection) for the k-th (1-based) eigenvalue of one block,
  * starting from [lo, hi] with count(lo) < k <= count(hi).  It runs to full
  * accuracy: until the width is at most max(2*omega, 2*eps*max(|lo|,|hi|)) or
@@ -272,7 +283,10 @@ static double orc_resid(int64_t n, const double *d, const double *e,
     return scale * sqrt(ssq);
 }
 
-static void orc_sign_fix(int64_t n, double *x)
+/* Sign convention shared with the GPU path: the entry of largest magnitude
+ * becomes positive; among entries of equal magnitude the lowest row decides
+ * (the strict comparison keeps the first maximum). */
+void orc_sign_fix(int64_t n, double *x)
 {
     int64_t im = 0;
     double am = -1.0;
@@ -488,25 +502,35 @@ int64_t orc_solve(int64_t n, const double *d, const double *e, int range,
     return mout;
 }
 
-/* Single eigenvalue by global index (1-based) of an unsplit matrix: used to
- * sample large problems one eigenvalue at a time. */
+/* Single eigenvalue by global index (1-based), to full accuracy, for
+ * sampling large problems one eigenvalue at a time.  The same steps as the
+ * whole solve: Gershgorin interval (Alg. B.3), the splitting of Sec. 3.2.1
+ * (entries at or below eps*sqrt(n)*bnorm set to zero), an interval checked
+ * to hold the whole spectrum, then bisection (Alg. 3.3) on the Sturm count
+ * of the split matrix.  With the split entries zero the count of T is the
+ * sum of the blocks' counts, so the k-th eigenvalue of T is the k-th of the
+ * direct sum of the blocks. */
 double orc_eigval_index(int64_t n, const double *d, const double *e, int64_t k)
 {
+    if (n <= 0 || k < 1 || k > n) return NAN;
+    if (n == 1) return d[0];
     double g[3];
     orc_gershgorin(n, d, e, g);
-    double pivmin = orc_pivmin(n, e);
-    return orc_bisect_k(n, d, e, k, g[0], g[1], pivmin);
-}
-
-/* Inverse-iteration vector for one isolated eigenvalue (no clustering). */
-void orc_eigvec_single(int64_t n, const double *d, const double *e,
-                       double lambda, double *x, uint64_t seed)
-{
-    double g[3];
-    orc_gershgorin(n, d, e, g);
-    int64_t gid = 0;
-    orc_cluster_vectors(n, d, e, g[2], &lambda, 0, 1, &gid, x, n, seed, 0);
-    orc_sign_fix(n, x);
+    int64_t *starts = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    int64_t nb = orc_split(n, e, g[2], starts);
+    double *es = (double *)malloc(sizeof(double) * (size_t)(n - 1));
+    for (int64_t i = 0; i < n - 1; ++i) es[i] = e[i];
+    for (int64_t b = 1; b < nb; ++b) es[starts[b] - 1] = 0.0;
+    double pivmin = orc_pivmin(n, es);
+    double lo = g[0], hi = g[1];
+    for (int t = 0; t < 64 && orc_negcount(n, d, es, lo, pivmin) > 0; ++t)
+        lo -= fmax(fabs(lo), 1.0);
+    for (int t = 0; t < 64 && orc_negcount(n, d, es, hi, pivmin) < n; ++t)
+        hi += fmax(fabs(hi), 1.0);
+    double lam = orc_bisect_k(n, d, es, k, lo, hi, pivmin);
+    free(es);
+    free(starts);
+    return lam;
 }
 
 /* ---------------------------------------------------------------------- */

@@ -26,7 +26,7 @@ from ._lib import MrrrError, Options, Stats, default_options  # noqa: F401
 __all__ = [
     "eigh_tridiagonal", "eigh_tridiagonal_batched", "eigh_tridiagonal_backward",
     "eigh_tridiagonal_backward_batched", "EighTridiagonal", "EighTridiagonalBatched",
-    "default_options", "MrrrError", "last_stats", "library_path",
+    "default_options", "MrrrError", "last_stats", "library_path", "batched_layout",
 ]
 
 _tls = threading.local()
@@ -61,6 +61,44 @@ def _dev_f64(x, name):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _check_len(t, need, name):
+    if t.numel() < need:
+        raise ValueError(f"{name} holds {t.numel()} entries, needs at least {need}")
+
+
+def batched_layout(n_offsets, z_offsets=None):
+    """Validated batch layout: (row offsets, z offsets, rows, Z entries).
+
+    n_offsets must start at 0 and never decrease; z_offsets (one per matrix,
+    default packed) must be non-negative, and the n_b x n_b blocks they
+    start may not overlap.  The Z entries needed are max_b(z_offsets[b] +
+    n_b^2)."""
+    noff = [int(x) for x in n_offsets]
+    if len(noff) < 1 or noff[0] != 0:
+        raise ValueError("n_offsets must start at 0")
+    batch = len(noff) - 1
+    sizes = [noff[b + 1] - noff[b] for b in range(batch)]
+    if any(nb < 0 for nb in sizes):
+        raise ValueError("n_offsets must not decrease")
+    if z_offsets is None:
+        zoff, acc = [], 0
+        for nb in sizes:
+            zoff.append(acc)
+            acc += nb * nb
+        return noff, None, noff[-1], acc
+    zoff = [int(x) for x in z_offsets]
+    if len(zoff) != batch:
+        raise ValueError(f"z_offsets must hold one entry per matrix ({batch}), got {len(zoff)}")
+    if any(z < 0 for z in zoff):
+        raise ValueError("z_offsets must be non-negative")
+    spans = sorted((zoff[b], zoff[b] + sizes[b] * sizes[b]) for b in range(batch) if sizes[b] > 0)
+    for (a0, a1), (b0, _) in zip(spans, spans[1:]):
+        if b0 < a1:
+            raise ValueError("the Z blocks of two matrices overlap")
+    ztot = max((z1 for _, z1 in spans), default=0)
+    return noff, zoff, noff[-1], ztot
 
 
 def last_stats() -> dict:
@@ -130,13 +168,12 @@ def eigh_tridiagonal_batched(d_cat, e_cat, n_offsets, z_offsets=None, eigvals_on
     """
     d_cat = _dev_f64(d_cat, "d_cat")
     e_cat = _dev_f64(e_cat, "e_cat")
-    noff = [int(x) for x in n_offsets]
+    noff, zoff, rows, ztot = batched_layout(n_offsets, z_offsets)
     batch = len(noff) - 1
+    _check_len(d_cat, rows, "d_cat")
+    _check_len(e_cat, rows, "e_cat")
     arr = (ctypes.c_int64 * (batch + 1))(*noff)
-    zarr = None
-    ztot = sum((noff[b + 1] - noff[b]) ** 2 for b in range(batch))
-    if z_offsets is not None:
-        zarr = (ctypes.c_int64 * batch)(*[int(x) for x in z_offsets])
+    zarr = (ctypes.c_int64 * batch)(*zoff) if zoff is not None else None
     o = _options(options, not eigvals_only)
     tune_arr = None
     if tune is not None:
@@ -146,6 +183,14 @@ def eigh_tridiagonal_batched(d_cat, e_cat, n_offsets, z_offsets=None, eigvals_on
         o.tune = tune_arr.ctypes.data
     if out is not None:
         w_cat, Z_cat = out
+        w_cat = _dev_f64(w_cat, "out[0]")
+        _check_len(w_cat, rows, "out[0] (w_cat)")
+        if not eigvals_only:
+            Z_cat = _dev_f64(Z_cat, "out[1]")
+            _check_len(Z_cat, ztot, "out[1] (Z_cat)")
+        if (w_cat.data_ptr() != out[0].data_ptr()
+                or (not eigvals_only and Z_cat.data_ptr() != out[1].data_ptr())):
+            raise ValueError("out buffers must be contiguous")
     else:
         w_cat = d_cat.new_empty(max(noff[-1], 1))
         Z_cat = d_cat.new_empty(max(ztot, 1)) if not eigvals_only else None
@@ -163,11 +208,18 @@ def eigh_tridiagonal_backward(w, Z, wbar=None, Zbar=None, gap_mask_rel=1e-8, cou
     is the (n, n) tensor returned by eigh_tridiagonal (column-major view)."""
     w = _dev_f64(w, "w")
     n = w.numel()
+    Z = _dev_f64(Z, "Z")
+    if tuple(Z.shape) != (n, n):
+        raise ValueError(f"Z must be ({n}, {n}) (all eigenpairs), got {tuple(Z.shape)}")
     Zc = Z.t().contiguous()          # column-major storage: (columns, rows)
     wb = _dev_f64(wbar, "wbar") if wbar is not None else None
+    if wb is not None and wb.numel() != n:
+        raise ValueError(f"wbar must hold {n} entries, got {wb.numel()}")
+    if Zbar is not None:
+        Zbar = _dev_f64(Zbar, "Zbar")
+        if tuple(Zbar.shape) != (n, n):
+            raise ValueError(f"Zbar must be ({n}, {n}), got {tuple(Zbar.shape)}")
     Zb = Zbar.t().contiguous() if Zbar is not None else None
-    if Zb is not None and Zb.dtype != torch.float64:
-        raise TypeError("Zbar must be float64")
     dbar = w.new_empty(max(n, 1))
     ebar = w.new_empty(max(n - 1, 1))
     nm = ctypes.c_int64(0)
@@ -184,12 +236,18 @@ def eigh_tridiagonal_backward_batched(w_cat, Z_cat, n_offsets, wbar_cat=None, Zb
                                       z_offsets=None, gap_mask_rel=1e-8, count_masked=False):
     w_cat = _dev_f64(w_cat, "w_cat")
     Z_cat = _dev_f64(Z_cat, "Z_cat")
-    noff = [int(x) for x in n_offsets]
+    noff, zoff, rows, ztot = batched_layout(n_offsets, z_offsets)
     batch = len(noff) - 1
+    _check_len(w_cat, rows, "w_cat")
+    _check_len(Z_cat, ztot, "Z_cat")
     arr = (ctypes.c_int64 * (batch + 1))(*noff)
-    zarr = (ctypes.c_int64 * batch)(*[int(x) for x in z_offsets]) if z_offsets is not None else None
+    zarr = (ctypes.c_int64 * batch)(*zoff) if zoff is not None else None
     wb = _dev_f64(wbar_cat, "wbar_cat") if wbar_cat is not None else None
     Zb = _dev_f64(Zbar_cat, "Zbar_cat") if Zbar_cat is not None else None
+    if wb is not None:
+        _check_len(wb, rows, "wbar_cat")
+    if Zb is not None:
+        _check_len(Zb, ztot, "Zbar_cat")
     dbar = w_cat.new_empty(max(noff[-1], 1))
     ebar = w_cat.new_empty(max(noff[-1], 1))
     nm = ctypes.c_int64(0)

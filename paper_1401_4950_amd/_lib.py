@@ -18,7 +18,7 @@ STATUS = {
 EXPORTS = (
     "mrrr_create", "mrrr_destroy", "mrrr_set_stream", "mrrr_default_options",
     "mrrr_status_string", "mrrr_dstemr", "mrrr_dstemr_batched",
-    "mrrr_dstemr_backward", "mrrr_dstemr_backward_batched",
+    "mrrr_dstemr_backward", "mrrr_dstemr_backward_batched", "mrrr_diag_quotient",
 )
 
 
@@ -54,6 +54,7 @@ class Stats(ctypes.Structure):
         ("arena_bytes", ctypes.c_int64), ("ms", ctypes.c_double), ("tree_ms", ctypes.c_double),
         ("n_sturm_guarded", ctypes.c_int64), ("n_checked", ctypes.c_int64),
         ("n_reorthogonalized", ctypes.c_int64), ("n_check_failed", ctypes.c_int64),
+        ("n_check_wide", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -93,6 +94,8 @@ def load():
     lib.mrrr_dstemr_backward.restype = i32
     lib.mrrr_dstemr_backward_batched.argtypes = [vp, i64, p64, vp, vp, p64, vp, vp, dbl, vp, vp, p64]
     lib.mrrr_dstemr_backward_batched.restype = i32
+    lib.mrrr_diag_quotient.argtypes = [vp, i64, vp, vp, vp]
+    lib.mrrr_diag_quotient.restype = i32
     _lib = lib
     return lib
 

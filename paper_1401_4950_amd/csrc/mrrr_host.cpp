@@ -23,6 +23,7 @@ hipError_t launch_finalize(const Params& P, hipStream_t s);
 hipError_t launch_sign(const Params& P, int64_t ncols_total, hipStream_t s);
 hipError_t launch_check(const Params& P, hipStream_t s);
 hipError_t tree_occupancy(int* blocks_per_cu);
+hipError_t launch_quot(const double* a, const double* b, double* q, int64_t n, hipStream_t s);
 int adjoint_run(hipStream_t s, int64_t batch, const int64_t* n_offsets_h, const int64_t* z_offsets_h,
                 const double* w, const double* Z, const double* wbar, const double* Zbar,
                 double gap_mask_rel, double* dbar, double* ebar, int64_t* n_masked_h, int64_t ldz_single,
@@ -362,6 +363,7 @@ void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms, float tree_
     st->n_checked = c.n_checked;
     st->n_reorthogonalized = c.n_repaired;
     st->n_check_failed = c.n_check_failed;
+    st->n_check_wide = c.n_check_wide;
     st->qd_steps = c.qd_steps;
     st->n_tasks = c.n_tasks;
     st->n_singleton_tasks = c.n_single;
@@ -575,6 +577,9 @@ extern "C" int mrrr_dstemr_batched(mrrr_handle_t h, int64_t batch, const int64_t
         if (n_offsets[b + 1] < n_offsets[b]) return -3;
     const int64_t rows = batch > 0 ? n_offsets[batch] : 0;
     if (rows > (int64_t)INT32_MAX / 2) return -3;
+    if (z_offsets)
+        for (int64_t b = 0; b < batch; ++b)
+            if (z_offsets[b] < 0) return -6;
     if (rows > 0 && !d_cat) return -4;
     if (rows > 0 && !e_cat) return -5;
     mrrr_options_t o;
@@ -671,6 +676,9 @@ extern "C" int mrrr_dstemr_backward_batched(mrrr_handle_t h, int64_t batch, cons
     const int64_t rows = batch > 0 ? n_offsets[batch] : 0;
     if (rows > 0 && !w_cat) return -4;
     if (rows > 0 && !Z_cat) return -5;
+    if (z_offsets)
+        for (int64_t b = 0; b < batch; ++b)
+            if (z_offsets[b] < 0) return -6;
     if (!(gap_mask_rel >= 0.0)) return -9;
     if (rows > 0 && !dbar_cat) return -10;
     if (rows > 0 && !ebar_cat) return -11;
@@ -679,4 +687,18 @@ extern "C" int mrrr_dstemr_backward_batched(mrrr_handle_t h, int64_t batch, cons
     if (hipSetDevice(h->device) != hipSuccess) return MRRR_EHIP;
     return adjoint_run(h->stream, batch, n_offsets, z_offsets, w_cat, Z_cat, wbar_cat, Zbar_cat, gap_mask_rel,
                        dbar_cat, ebar_cat, n_masked, -1, -1, adj_alloc, &h->adj);
+}
+
+// ---------------------------------------------------------------- diagnostics
+
+extern "C" int mrrr_diag_quotient(mrrr_handle_t h, int64_t n, const double* a, const double* b, double* q) {
+    if (!h) return -1;
+    if (n < 0 || n > ((int64_t)1 << 40)) return -2;
+    if (n > 0 && !a) return -3;
+    if (n > 0 && !b) return -4;
+    if (n > 0 && !q) return -5;
+    if (n == 0) return MRRR_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return MRRR_EHIP;
+    if (launch_quot(a, b, q, n, h->stream) != hipSuccess) return MRRR_EHIP;
+    return MRRR_OK;
 }

@@ -132,6 +132,7 @@ struct Ctl {
     int64_t n_sturm;
     int64_t chk_top;      // records in Params::chk
     int64_t n_checked, n_repaired, n_check_failed;
+    int64_t n_check_wide; // unverified clusters too wide to be checked themselves
 #ifdef __HIPCC__
     __device__ __host__ uint64_t* head(int q) { return head_ + q * kLineU64; }
     __device__ __host__ uint64_t* tail(int q) { return tail_ + q * kLineU64; }

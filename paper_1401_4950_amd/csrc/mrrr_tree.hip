@@ -2592,9 +2592,6 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     C.slot_base = sb;
     C.publish = true;
     C.lanes = P.probs[blk.prob].lanes;
-#ifdef MRRR_DEBUG_TRACE
-    const double dbg_lo_in = ld_rlx_d(P.lo + sb + p), dbg_hi_in = ld_rlx_d(P.hi + sb + p);
-#endif
     // long representations: with idle workers' help when there are any (the
     // brackets are those of the sequential schedule either way)
     bool ends_done = false;
@@ -2715,6 +2712,8 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
                 } else {
                     add_stat(&P.ctl->n_check_failed, 1);
                 }
+            } else if (m > kCheckMax) {
+                add_stat(&P.ctl->n_check_wide, 1);
             }
         }
         Node nd;
@@ -2776,12 +2775,6 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         S.info_i[2] = id;
         S.info_d[0] = tau;
         S.info_d[1] = chosen_growth;
-#ifdef MRRR_DEBUG_TRACE
-        S.info_d[0] = lo_p;
-        S.info_d[1] = dbg_lo_in;
-        S.info_i[1] = (int)(S.m_flag[0] & 3);
-        (void)dbg_hi_in;
-#endif
     }
     add_stat(&P.ctl->n_nodes, 1);
     add_stat(&P.ctl->n_unverified, unverified);
@@ -3374,9 +3367,22 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_sign_kernel(Params P, int6
     }
 }
 
+// The reciprocal-based quotient (quot) element by element, for checking it
+// against IEEE division on the device that runs the kernels.
+extern "C" __global__ void mrrr_quot_kernel(const double* a, const double* b, double* q, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) q[i] = quot(recip(b[i]), a[i]);
+}
+
 // ------------------------------------------------------------ launchers
 
 namespace mrrr {
+
+hipError_t launch_quot(const double* a, const double* b, double* q, int64_t n, hipStream_t s) {
+    const int64_t grid = (n + 255) / 256;
+    if (grid > 0) hipLaunchKernelGGL(mrrr_quot_kernel, dim3((unsigned)grid), dim3(256), 0, s, a, b, q, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_init(const Params& P, hipStream_t s) {
     uint64_t mx = 1;

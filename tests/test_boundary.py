@@ -73,3 +73,56 @@ def test_package_has_no_cpu_path():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 txt = open(os.path.join(dp, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+def test_batched_layout_validation():
+    """The binding sizes and checks the batched layout on the host, before
+    anything reaches the C ABI: Z entries follow the z offsets, bad offsets
+    and overlapping Z blocks are refused."""
+    from paper_1401_4950_amd import batched_layout
+    noff, zoff, rows, ztot = batched_layout([0, 3, 5, 5, 9])
+    assert noff == [0, 3, 5, 5, 9] and zoff is None and rows == 9 and ztot == 9 + 4 + 0 + 16
+    # a spread layout needs max(z_b + n_b^2) entries, not sum n_b^2
+    _, zoff, _, ztot = batched_layout([0, 3, 5], z_offsets=[100, 0])
+    assert zoff == [100, 0] and ztot == 109
+    _, _, _, ztot = batched_layout([0, 2, 2, 4], z_offsets=[0, 3, 4])   # empty matrix: any offset
+    assert ztot == 8
+    for bad in ([1, 3], [0, 3, 2], []):
+        with pytest.raises(ValueError):
+            batched_layout(bad)
+    with pytest.raises(ValueError):
+        batched_layout([0, 3, 5], z_offsets=[-1, 10])
+    with pytest.raises(ValueError):
+        batched_layout([0, 3, 5], z_offsets=[0, 8])          # 3x3 block ends at 9
+    with pytest.raises(ValueError):
+        batched_layout([0, 3, 5], z_offsets=[0])             # one offset per matrix
+
+
+def test_negative_z_offsets_refused_by_the_c_abi(lib):
+    """The library itself refuses negative Z offsets (argument 6) before any
+    device work, so a caller of the C ABI cannot make it write below Z."""
+    from paper_1401_4950_amd import _lib
+    noff = (ctypes.c_int64 * 3)(0, 3, 5)
+    zoff = (ctypes.c_int64 * 2)(0, -9)
+    o = _lib.default_options()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    h = ctypes.c_void_p(0x1000)
+    assert lib.mrrr_dstemr_batched(h, 2, noff, fake, fake, zoff, ctypes.byref(o), fake, fake, None) == -6
+    assert lib.mrrr_dstemr_backward_batched(h, 2, noff, fake, fake, zoff, None, None, 1e-8, fake, fake,
+                                            None) == -6
+
+
+def _header_fields(struct_name):
+    hdr = open(os.path.join(ROOT, "include", "mrrr.h")).read()
+    head = hdr[: re.search(r"\}\s*" + struct_name + r";", hdr).start()]
+    body = head[head.rindex("typedef struct {") + len("typedef struct {"):]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return re.findall(r"\b(?:int32_t|int64_t|uint64_t|double|void\s*\*|const int32_t\s*\*)\s*\**\s*(\w+)\s*;",
+                      body)
+
+
+@pytest.mark.parametrize("struct,mirror", [("mrrr_stats_t", "Stats"), ("mrrr_options_t", "Options")])
+def test_ctypes_mirrors_follow_the_header(struct, mirror):
+    """The binding's ctypes structures list the header's fields in order."""
+    from paper_1401_4950_amd import _lib
+    assert _header_fields(struct) == [f for f, _ in getattr(_lib, mirror)._fields_]

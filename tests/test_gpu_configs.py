@@ -1,0 +1,335 @@
+"""Parity at the sizes of the benchmark configurations, through the C ABI.
+
+C2: all eigenpairs of four n = 20000 matrices -- every eigenvalue against
+    the oracle's bisection, the residual of every column and all of Z^T Z on
+    the GPU, and sampled well-separated vectors against the oracle's inverse
+    iteration (1-2-1: against the sine closed form).
+C3: indices 1..5000 of n = 50000 -- every eigenvalue against the oracle.
+C4: 4096 matrices of sizes log-uniform in [32, 2048] -- every matrix's
+    residual and orthogonality, every eigenvalue certified by two Sturm
+    counts of the oracle, 64 matrices against the oracle's full solve.
+C5: forward + backward -- 256 x n = 512 against the oracle gradient; n = 8192
+    against central differences (h = 1e-6, with h = 5e-7 to flag where the
+    difference quotient itself is unreliable) and the gradient identities;
+    glued Wilkinson n = 8192 on cluster sums, where single eigenvalues of a
+    numerically tight cluster have no well-defined derivative.
+"""
+import numpy as np
+import pytest
+
+import tridiag_inputs as ti
+from oracle import metrics as M
+
+pytestmark = pytest.mark.gpu
+
+from _gpu_util import EPS, check_pairs, gpu_residual_orth, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _gaps(w):
+    g = np.diff(w)
+    return np.minimum(np.r_[np.inf, g], np.r_[g, np.inf])
+
+
+def _signed_or_abs_dot(z, zo):
+    """z . z_oracle, signed when the oracle's largest entry stands clear of
+    the runner-up (then the sign convention decides the sign on both sides),
+    else its absolute value."""
+    a = np.sort(np.abs(zo))
+    dot = float(z @ zo)
+    return dot if a[-1] - a[-2] > 1e-6 * a[-1] else abs(dot)
+
+
+def _sampled_vectors(orc, d, e, w_gpu, Z_gpu, wo, tn, count=8):
+    """Columns whose oracle gap is at least 1e-5 ||T||, spread over the
+    spectrum, against the oracle's vector for that index alone."""
+    gaps = _gaps(wo)
+    cand = np.nonzero(gaps >= 1e-5 * tn)[0]
+    if len(cand) == 0:
+        return 0
+    pick = cand[np.unique(np.linspace(0, len(cand) - 1, count).astype(int))]
+    for k in pick:
+        _, zo = orc.solve(d, e, "index", il=int(k) + 1, iu=int(k) + 1)
+        z = Z_gpu[:, int(k)].cpu().numpy()
+        dot = _signed_or_abs_dot(z, zo[:, 0])
+        assert dot >= 1 - 1e-10, (int(k), dot, gaps[k] / tn)
+    return len(pick)
+
+
+# ------------------------------------------------------------------- C2
+
+
+@pytest.mark.parametrize("fam", ["121", "clement", "glued_wilkinson", "random"])
+def test_config2_n20000(orc, fam):
+    import torch
+    import paper_1401_4950_amd as mr
+    n = 20000
+    d, e = ti.family(fam, n, 0)
+    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e))
+    torch.cuda.synchronize()
+    wo = orc.solve(d, e, vectors=False)
+    tn = M.tnorm_of(wo)
+    wh = w.cpu().numpy()
+    assert np.all(np.diff(wh) >= 0)
+    err = np.max(np.abs(wh - wo)) / (n * EPS * tn)
+    assert err <= 4, f"eigenvalue error {err:.2f} n eps ||T||"
+    res, orth = gpu_residual_orth(d, e, w, Z, tn)
+    assert res <= 10 and orth <= 100, (res, orth)
+    if fam == "121":
+        # sine eigenvectors (App. D), individually where the gap allows
+        gaps = _gaps(wo)
+        idx = np.nonzero(gaps >= 1e-5 * tn)[0]
+        idx = idx[np.unique(np.linspace(0, len(idx) - 1, 16).astype(int))]
+        i = np.arange(1, n + 1)[:, None]
+        S = M.sign_normalize(np.sqrt(2.0 / (n + 1)) * np.sin(i * (idx[None, :] + 1) * np.pi / (n + 1)))
+        dots = np.abs(np.sum(Z[:, idx].cpu().numpy() * S, axis=0))
+        assert np.all(dots >= 1 - 1e-10), dots
+    else:
+        _sampled_vectors(orc, d, e, w, Z, wo, tn)
+
+
+# ------------------------------------------------------------------- C3
+
+
+@pytest.mark.parametrize("fam", ["random", "glued_wilkinson"])
+def test_config3_subset_n50000(orc, fam):
+    import torch
+    import paper_1401_4950_amd as mr
+    n, k = 50000, 5000
+    d, e = ti.family(fam, n, 0)
+    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e), select="i", select_range=(1, k))
+    torch.cuda.synchronize()
+    assert w.shape[0] == k and Z.shape == (n, k)
+    wo = orc.solve(d, e, "index", il=1, iu=k, vectors=False)
+    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
+    wh = w.cpu().numpy()
+    err = np.max(np.abs(wh - wo)) / (n * EPS * tn)
+    assert err <= 4, f"eigenvalue error {err:.2f} n eps ||T||"
+    res, orth = gpu_residual_orth(d, e, w, Z, tn)
+    assert res <= 10 and orth <= 100, (res, orth)
+    if fam == "random":
+        assert _sampled_vectors(orc, d, e, w, Z, wo, tn) > 0
+
+
+# ------------------------------------------------------------------- C4
+
+
+def test_batched_config4_every_matrix(orc):
+    """4096 matrices, sizes log-uniform in [32, 2048], e in [0.1, 1]: for
+    every matrix the residual of every column and Z^T Z on the GPU, and every
+    eigenvalue certified by the oracle's Sturm counts: fewer than i
+    eigenvalues lie below w_i - tol and at least i below w_i + tol, with
+    tol = 4 n eps ||T||.  64 matrices against the oracle's whole solve."""
+    import torch
+    import paper_1401_4950_amd as mr
+    sizes, off, d_cat, e_cat = ti.batch_uniform(4096, seed=0)
+    w_cat, Z_cat = mr.eigh_tridiagonal_batched(to_dev(d_cat), to_dev(e_cat), off)
+    torch.cuda.synchronize()
+    wh_cat = w_cat.cpu().numpy()
+    rng = np.random.default_rng(1)
+    pick = set(rng.choice(len(sizes), 64, replace=False).tolist())
+    zo = 0
+    worst_r = worst_o = 0.0
+    for b, nb in enumerate(sizes):
+        nb = int(nb)
+        r0 = int(off[b])
+        Zb = Z_cat[zo:zo + nb * nb].view(nb, nb).T
+        wb = w_cat[r0:r0 + nb]
+        d = d_cat[r0:r0 + nb]
+        e = e_cat[r0:r0 + nb - 1]
+        wh = wh_cat[r0:r0 + nb]
+        tn = float(np.max(np.abs(wh)))
+        r, o = gpu_residual_orth(d, e, wb, Zb, tn)
+        worst_r, worst_o = max(worst_r, r), max(worst_o, o)
+        assert np.all(np.diff(wh) >= 0), b
+        tol = 4 * nb * EPS * tn
+        c = orc.negcounts(d, e, np.concatenate([wh - tol, wh + tol]))
+        i = np.arange(1, nb + 1)
+        assert np.all(c[:nb] <= i - 1) and np.all(c[nb:] >= i), f"matrix {b}: eigenvalue outside its Sturm bracket"
+        if b in pick:
+            wo, Zo = orc.solve(d, e)
+            check_pairs(d, e, wh, Zb.cpu().numpy(), wo, Zo)
+        zo += nb * nb
+    assert worst_r <= 10 and worst_o <= 100, (worst_r, worst_o)
+
+
+# ------------------------------------------------------------------- C5
+
+
+def _rel_err(g, go):
+    return float(np.max(np.abs(g - go)) / max(np.max(np.abs(go)), 1e-300))
+
+
+def test_grad_config5_batch256_n512(orc):
+    """Loss sum c_i lambda_i + <G, Z> over 256 random n = 512 matrices,
+    fused batched forward + backward, against the oracle gradient of each
+    matrix (the oracle's vectors take the GPU's signs first: the loss's
+    eigenvector term is defined on the branch the forward returned).  Pairs
+    closer than 1e-8 ||T|| are masked on both sides and counted."""
+    import torch
+    from paper_1401_4950_amd import EighTridiagonalBatched
+    B, n = 256, 512
+    sizes, off, d_cat, e_cat = ti.batch_uniform(B, seed=5, sizes=[n] * B, elo=-1.0, ehi=1.0)
+    rng = np.random.default_rng(11)
+    c = rng.standard_normal(B * n)
+    G = rng.standard_normal(B * n * n)
+    dt = to_dev(d_cat).requires_grad_(True)
+    et = to_dev(e_cat).requires_grad_(True)
+    w, Z = EighTridiagonalBatched.apply(dt, et, off)
+    ((to_dev(c) * w).sum() + (to_dev(G) * Z).sum()).backward()
+    torch.cuda.synchronize()
+    gd_all, ge_all = dt.grad.cpu().numpy(), et.grad.cpu().numpy()
+    Zh = Z.detach().cpu().numpy()
+    worst, min_gap, masked = 0.0, np.inf, 0
+    for b in range(B):
+        r0 = b * n
+        d, e = d_cat[r0:r0 + n], e_cat[r0:r0 + n - 1]
+        Zb = Zh[b * n * n:(b + 1) * n * n].reshape(n, n).T
+        Gb = G[b * n * n:(b + 1) * n * n].reshape(n, n).T
+        wo, Zo = orc.solve(d, e)
+        sgn = np.sign(np.sum(Zo * Zb, axis=0))
+        sgn[sgn == 0] = 1.0
+        Zo = Zo * sgn[None, :]
+        tn = M.tnorm_of(wo)
+        god, goe, nm = orc.grad(wo, Zo, c[r0:r0 + n], Gb, tnorm=tn)
+        masked += nm
+        g = np.concatenate([gd_all[r0:r0 + n], ge_all[r0:r0 + n - 1]])
+        go = np.concatenate([god, goe])
+        worst = max(worst, _rel_err(g, go))
+        gp = np.diff(wo)
+        min_gap = min(min_gap, float(np.min(gp[gp >= 1e-8 * tn])) / tn)
+        assert abs(ge_all[r0 + n - 1]) == 0.0          # the pad slot stays zero
+    print(f"C5(i): worst rel err {worst:.2e}, smallest unmasked relative gap {min_gap:.2e}, "
+          f"estimate n eps/gap {n * EPS / min_gap:.2e}, masked pairs {masked}")
+    assert worst <= 1e-6, worst
+
+
+def _fd_check(loss, x0, dirs, scale, h=1e-6):
+    """Central differences of loss along each direction at h and h/2.
+    Returns (fd, flagged): flagged where the two disagree by more than 1e-6
+    relative (the difference quotient is then dominated by curvature or by a
+    jump, e.g. a near crossing)."""
+    fds, flags = [], []
+    for v in dirs:
+        f1 = (loss(x0 + h * v) - loss(x0 - h * v)) / (2 * h)
+        f2 = (loss(x0 + 0.5 * h * v) - loss(x0 - 0.5 * h * v)) / h
+        fds.append(f1)
+        flags.append(abs(f1 - f2) > 1e-6 * max(abs(f1), scale))
+    return np.array(fds), np.array(flags)
+
+
+def test_grad_config5_n8192_fd_and_identities():
+    """n = 8192 random, loss sum c_i lambda_i + <G, Z>: 64 sampled
+    coordinates plus one seeded direction against central differences of
+    the forward solve; the eigenvalue part alone against the identities
+    sum_j dlambda_i/dd_j = 1, sum_i dlambda_i/dd_j = 1 and degree-1
+    homogeneity."""
+    import torch
+    import paper_1401_4950_amd as mr
+    from paper_1401_4950_amd import EighTridiagonal, eigh_tridiagonal_backward
+    n = 8192
+    d0, e0 = ti.random_uniform(n, 0)
+    c = np.random.default_rng(12).standard_normal(n)
+    G = np.random.default_rng(13).standard_normal((n, n))
+    ct, Gt = to_dev(c), to_dev(G)
+    dt = to_dev(d0).requires_grad_(True)
+    et = to_dev(e0).requires_grad_(True)
+    w, Z = EighTridiagonal.apply(dt, et)
+    ((ct * w).sum() + (Gt * Z).sum()).backward()
+    torch.cuda.synchronize()
+    g = np.concatenate([dt.grad.cpu().numpy(), et.grad.cpu().numpy()])
+
+    def loss(x):
+        ww, ZZ = mr.eigh_tridiagonal(to_dev(x[:n]), to_dev(x[n:]))
+        return float((ct * ww).sum() + (Gt * ZZ).sum())
+
+    x0 = np.concatenate([d0, e0])
+    rng = np.random.default_rng(21)
+    coords = np.concatenate([rng.choice(n, 32, replace=False), n + rng.choice(n - 1, 32, replace=False)])
+    dirs = [np.eye(1, 2 * n - 1, k)[0] for k in coords]
+    v = rng.standard_normal(2 * n - 1)
+    dirs.append(v / np.linalg.norm(v))
+    an = np.array([g @ u for u in dirs])
+    scale = float(np.max(np.abs(g)))
+    fd, flag = _fd_check(loss, x0, dirs, 1e-6 * scale)
+    ok = ~flag
+    rel = np.abs(fd - an) / np.maximum(np.abs(an), 1e-6 * scale)
+    print(f"C5(ii): {int(flag.sum())} of {len(dirs)} difference quotients flagged unreliable; "
+          f"worst rel err of the rest {float(np.max(rel[ok])) if ok.any() else float('nan'):.2e}")
+    assert ok.sum() >= 48
+    assert np.all(rel[ok] <= 1e-5), (rel[ok].max(), coords)
+    # identities of the eigenvalue derivatives
+    wd = w.detach()
+    for i in (0, 1234, n - 1):
+        wbar = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        wbar[i] = 1.0
+        dbar, ebar = eigh_tridiagonal_backward(wd, Z.detach(), wbar=wbar)
+        db, eb = dbar.cpu().numpy(), ebar.cpu().numpy()
+        assert abs(db.sum() - 1.0) <= 1e-10
+        lam = float(wd[i])
+        assert abs(d0 @ db + e0 @ eb - lam) <= 1e-10 * max(1.0, abs(lam))
+    dbar, ebar = eigh_tridiagonal_backward(wd, Z.detach(), wbar=torch.ones(n, dtype=torch.float64,
+                                                                          device="cuda:0"))
+    assert float((dbar - 1.0).abs().max()) <= 1e-10 and float(ebar.abs().max()) <= 1e-10
+
+
+def test_grad_config5_glued_wilkinson_n8192_cluster_sums():
+    """Glued Wilkinson n = 8192, eigenvalue loss: the eigenvalues come in
+    clusters closer than 1e-8 ||T||, inside which a single eigenvalue's
+    derivative depends on the basis.  The sum over a cluster is smooth: its
+    gradient (the projector diagonal sum_i z_ij^2 and 2 sum_i z_ij z_i,j+1)
+    is checked against central differences of the sum of the cluster's
+    eigenvalues and against the trace identity sum_j d(sum lambda)/dd_j =
+    |C|; every member of a multi-member cluster counts as masked."""
+    import torch
+    import paper_1401_4950_amd as mr
+    from paper_1401_4950_amd import EighTridiagonal, eigh_tridiagonal_backward
+    n = 8192
+    d0, e0 = ti.glued_wilkinson(n)
+    c = np.random.default_rng(12).standard_normal(n)
+    dt = to_dev(d0).requires_grad_(True)
+    et = to_dev(e0).requires_grad_(True)
+    w, Z = EighTridiagonal.apply(dt, et)
+    (to_dev(c) * w).sum().backward()
+    torch.cuda.synchronize()
+    wh = w.detach().cpu().numpy()
+    tn = M.tnorm_of(wh)
+    starts = np.r_[0, np.nonzero(np.diff(wh) >= 1e-8 * tn)[0] + 1, n]
+    clusters = [(int(a), int(b)) for a, b in zip(starts[:-1], starts[1:])]
+    multi = [ab for ab in clusters if ab[1] - ab[0] > 1]
+    masked = sum(b - a for a, b in multi)
+    print(f"C5(iii): {len(clusters)} clusters, {len(multi)} with several members, {masked} members masked")
+    assert multi
+    # the full loss: its gradient is the sum over clusters of c-weighted terms;
+    # its trace identity needs no basis: sum_j dL/dd_j = sum_i c_i
+    assert abs(float(dt.grad.sum()) - c.sum()) <= 1e-9 * np.sum(np.abs(c))
+    rng = np.random.default_rng(31)
+    x0 = np.concatenate([d0, e0])
+    for (a, b) in [multi[0], multi[len(multi) // 2], multi[-1]]:
+        wbar = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        wbar[a:b] = 1.0
+        dbar, ebar = eigh_tridiagonal_backward(w.detach(), Z.detach(), wbar=wbar)
+        gC = np.concatenate([dbar.cpu().numpy(), ebar.cpu().numpy()])
+        assert abs(gC[:n].sum() - (b - a)) <= 1e-9 * (b - a)
+
+        def s_c(x, a=a, b=b):
+            ww = mr.eigh_tridiagonal(to_dev(x[:n]), to_dev(x[n:]), select="i", select_range=(a + 1, b),
+                                     eigvals_only=True)
+            return float(ww.sum())
+
+        top = np.argsort(-np.abs(gC))[:24]
+        coords = np.concatenate([top, rng.choice(2 * n - 1, 8, replace=False)])
+        dirs = [np.eye(1, 2 * n - 1, k)[0] for k in coords]
+        an = np.array([gC[k] for k in coords])
+        scale = float(np.max(np.abs(gC)))
+        fd, flag = _fd_check(s_c, x0, dirs, 1e-6 * scale)
+        ok = ~flag
+        rel = np.abs(fd - an) / np.maximum(np.abs(an), 1e-6 * scale)
+        assert ok.sum() >= 24, (a, b, int(flag.sum()))
+        assert np.all(rel[ok] <= 1e-5), (a, b, rel[ok].max())

@@ -366,47 +366,6 @@ def test_stats_and_trace():
     assert int(rec[rec["type"] == 4]["b"].sum()) == 2000
 
 
-# ------------------------------------------------------- full-size configs
-
-
-@pytest.mark.parametrize("fam", ["121", "clement", "glued_wilkinson", "random"])
-def test_config2_n20000(orc, fam):
-    """n = 20000, all pairs: sampled eigenvalues against the oracle's
-    bisection, residual of every column, orthogonality of all of Z^T Z."""
-    import torch
-    import paper_1401_4950_amd as mr
-    n = 20000
-    d, e = ti.family(fam, n, 0)
-    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e))
-    torch.cuda.synchronize()
-    idx = np.unique(np.linspace(1, n, 48).astype(int))
-    wo = np.array([orc.eigval_index(d, e, int(k)) for k in idx])
-    wh = w.cpu().numpy()
-    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
-    assert np.all(np.diff(wh) >= 0)
-    assert np.max(np.abs(wh[idx - 1] - wo)) <= 4 * n * EPS * tn
-    res, orth = gpu_residual_orth(d, e, w, Z, tn)
-    assert res <= 10 and orth <= 100, (res, orth)
-
-
-@pytest.mark.parametrize("fam", ["random", "glued_wilkinson"])
-def test_config3_subset_n50000(orc, fam):
-    import torch
-    import paper_1401_4950_amd as mr
-    n, k = 50000, 5000
-    d, e = ti.family(fam, n, 0)
-    w, Z = mr.eigh_tridiagonal(to_dev(d), to_dev(e), select="i", select_range=(1, k))
-    torch.cuda.synchronize()
-    assert w.shape[0] == k and Z.shape == (n, k)
-    idx = np.unique(np.linspace(1, k, 24).astype(int))
-    wo = np.array([orc.eigval_index(d, e, int(j)) for j in idx])
-    tn = max(abs(orc.eigval_index(d, e, 1)), abs(orc.eigval_index(d, e, n)))
-    wh = w.cpu().numpy()
-    assert np.max(np.abs(wh[idx - 1] - wo)) <= 4 * n * EPS * tn
-    res, orth = gpu_residual_orth(d, e, w, Z, tn)
-    assert res <= 10 and orth <= 100, (res, orth)
-
-
 def test_split_blocks_with_interleaved_spectra(orc):
     """Two blocks whose eigenvalues interleave: the final merge permutes the
     columns along long cycles."""

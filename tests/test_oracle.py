@@ -217,3 +217,105 @@ def test_gradient_gap_mask_counts(orc):
     _, _, nm = orc.grad(w, Z, c, G, gap_mask_rel=1e-8)
     # the two glued W21+ copies have pairs closer than 1e-8 ||T||
     assert nm > 0 and nm % 2 == 0
+
+
+# ------------------------------------------- single eigenvalues by index
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 401])
+def test_eigval_index_closed_forms(orc, n):
+    """The k-th eigenvalue by itself against the closed forms of App. D:
+    1-2-1 (2 - 2 cos(k pi/(n+1))) and Clement (-(n-1) + 2(k-1))."""
+    ks = sorted({1, 2, n // 2, n - 1, n} & set(range(1, n + 1)))
+    d, e = ti.one_two_one(n)
+    for k in ks:
+        lam = 2.0 - 2.0 * np.cos(np.pi * k / (n + 1))
+        assert abs(orc.eigval_index(d, e, k) - lam) <= 4 * n * EPS * 4.0, (n, k)
+    d, e = ti.clement(n)
+    for k in ks:
+        assert abs(orc.eigval_index(d, e, k) - (-(n - 1) + 2.0 * (k - 1))) <= 4 * n * EPS * max(n - 1, 1), (n, k)
+
+
+@pytest.mark.parametrize("fam", ["random", "121", "clement", "glued_wilkinson", "hermite"])
+def test_eigval_index_against_jacobi(orc, fam):
+    """Every index of a 40 x 40 matrix against brute-force Jacobi."""
+    n = 40
+    d, e = ti.family(fam, n, 3)
+    wj, _ = orc.jacobi_tridiag(d, e)
+    got = np.array([orc.eigval_index(d, e, k) for k in range(1, n + 1)])
+    assert np.max(np.abs(got - wj)) <= 20 * n * EPS * np.linalg.norm(orc.dense(d, e)), fam
+
+
+@pytest.mark.parametrize("fam", ["random", "121", "clement", "glued_wilkinson"])
+def test_eigval_index_equals_solve_bit_for_bit(orc, fam):
+    """On a matrix that does not split, the sampled eigenvalue takes exactly
+    the steps of the whole solve (same interval, same bisection), so the two
+    agree bit for bit at every index, first and last included."""
+    n = 630
+    d, e = ti.family(fam, n, 0)
+    assert len(orc.split_points(d, e)) == 2
+    w = orc.solve(d, e, vectors=False)
+    for k in (1, 2, 17, n // 2, n - 1, n):
+        assert orc.eigval_index(d, e, k) == w[k - 1], (fam, k)
+
+
+def test_eigval_index_on_split_matrices(orc):
+    """Blocks separated by an exact zero coupling and by a coupling below
+    the splitting threshold: the k-th eigenvalue of T is the k-th of the
+    sorted union of the blocks' spectra (Jacobi on each block), and it
+    agrees with the whole solve, which bisects block by block, to within the
+    stopping width of the bisection."""
+    d1, e1 = ti.random_uniform(30, 4)
+    d2, e2 = ti.random_uniform(25, 5)
+    d3, e3 = ti.glued_wilkinson(21)
+    d = np.concatenate([d1, d2 + 0.01, d3 * 0.1])
+    e = np.concatenate([e1, [0.0], e2, [1e-300], e3])
+    n = len(d)
+    assert list(orc.split_points(d, e)) == [0, 30, 55, 76]
+    ref = np.sort(np.concatenate([orc.jacobi_tridiag(d1, e1)[0], orc.jacobi_tridiag(d2 + 0.01, e2)[0],
+                                  orc.jacobi_tridiag(d3 * 0.1, e3)[0]]))
+    got = np.array([orc.eigval_index(d, e, k) for k in range(1, n + 1)])
+    tn = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 20 * n * EPS * tn
+    w = orc.solve(d, e, vectors=False)
+    assert np.all(np.abs(got - w) <= 4 * EPS * np.maximum(np.abs(w), 1e-300) + 1e-300)
+
+
+# ----------------------------------------------------------- sign convention
+
+
+def test_sign_fix_convention(orc):
+    """Largest magnitude made positive; among equal magnitudes the lowest row
+    decides; a vector already in the convention, and the zero vector, are
+    left alone."""
+    assert np.array_equal(orc.sign_fix([0.5, -0.7, 0.7, 0.1]), [-0.5, 0.7, -0.7, -0.1])
+    assert np.array_equal(orc.sign_fix([0.5, 0.7, -0.7, 0.1]), [0.5, 0.7, -0.7, 0.1])
+    assert np.array_equal(orc.sign_fix([-3.0, 1.0, 2.0]), [3.0, -1.0, -2.0])
+    assert np.array_equal(orc.sign_fix([-0.25, 0.25, -0.25]), [0.25, -0.25, 0.25])
+    assert np.array_equal(orc.sign_fix([0.0, 0.0]), [0.0, 0.0])
+    assert np.array_equal(orc.sign_fix([-1e-300]), [1e-300])
+    # the Python helper used on closed-form vectors follows the same rule
+    X = np.array([[0.5, -0.2, -3.0], [-0.7, 0.2, 1.0], [0.7, 0.1, 2.0]])
+    assert np.array_equal(M.sign_normalize(X), np.stack([orc.sign_fix(X[:, j]) for j in range(3)], axis=1))
+
+
+@pytest.mark.parametrize("fam", ["random", "clement", "glued_wilkinson"])
+def test_solve_vectors_follow_sign_convention(orc, fam):
+    d, e = ti.family(fam, 200, 2)
+    _, Z = orc.solve(d, e)
+    idx = np.argmax(np.abs(Z), axis=0)
+    assert np.all(Z[idx, np.arange(Z.shape[1])] > 0)
+
+
+def test_negcounts_many_shifts(orc):
+    """The many-shift count equals the one-shift count at every shift, and
+    away from eigenvalues it is exactly #(w < s) for the returned spectrum."""
+    d, e = ti.random_uniform(250, 8)
+    w = orc.solve(d, e, vectors=False)
+    rng = np.random.default_rng(5)
+    s = np.concatenate([rng.uniform(w[0] - 1, w[-1] + 1, 200), w, [w[0] - 10, w[-1] + 10]])
+    c = orc.negcounts(d, e, s)
+    assert np.array_equal(c, [orc.negcount(d, e, x) for x in s])
+    far = np.array([np.min(np.abs(w - x)) > 1e-9 for x in s])
+    assert np.array_equal(c[far], [int(np.sum(w < x)) for x in s[far]])
+    assert c[-2] == 0 and c[-1] == 250
