@@ -246,6 +246,33 @@ int mrrr_dstemr_backward_batched(mrrr_handle_t h, int64_t batch,
                                  double gap_mask_rel, double *dbar_cat,
                                  double *ebar_cat, int64_t *n_masked);
 
+/* Largest n that mrrr_dstemr_backward_noalloc accepts with an eigenvector
+ * cotangent (Zbar non-NULL). */
+#define MRRR_BACKWARD_NOALLOC_MAX_N 2048
+
+/* mrrr_dstemr_backward without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Arguments, layout and results are those
+ * of mrrr_dstemr_backward (same kernels, same values bit for bit).  Instead
+ * of the handle's growing workspace it uses one fixed device array per GPU
+ * (about 36 MB, held by every GPU the library runs on until the process
+ * ends): the problem record, the mask counter, M and the partial sums.
+ * Its address is taken once per handle at mrrr_create.
+ *   n        with Zbar non-NULL, 0 <= n <= MRRR_BACKWARD_NOALLOC_MAX_N, else
+ *            -2 is returned before anything is launched; without Zbar any n.
+ * Every call on one GPU shares that GPU's array and overwrites it (the
+ * counter is cleared by the call itself): calls that overlap on one GPU,
+ * from any handle or stream, race and must be serialised by the caller.
+ * The call launches kernels only (no memset, no host-to-device copy); with
+ * n_masked non-NULL and Zbar non-NULL it copies the count back and
+ * synchronises the stream.
+ * Errors: negative argument index, MRRR_EHIP (includes a device on which the
+ * array's address could not be taken). */
+int mrrr_dstemr_backward_noalloc(mrrr_handle_t h, int64_t n, const double *w,
+                                 const double *Z, int64_t ldz, const double *wbar,
+                                 const double *Zbar, int64_t ldzbar, double gap_mask_rel,
+                                 double *dbar, double *ebar, int64_t *n_masked);
+
 /* Diagnostic: q[i] = a[i] / b[i] by the quotient the kernels use where the
  * shift selection of Alg. 3.8 and a new representation's rows need
  * quotients (the hardware reciprocal, one Newton step and Markstein's

@@ -25,7 +25,8 @@ from ._lib import MrrrError, Options, Stats, default_options  # noqa: F401
 
 __all__ = [
     "eigh_tridiagonal", "eigh_tridiagonal_batched", "eigh_tridiagonal_backward",
-    "eigh_tridiagonal_backward_batched", "EighTridiagonal", "EighTridiagonalBatched",
+    "eigh_tridiagonal_backward_batched", "eigh_tridiagonal_backward_noalloc", "EighTridiagonal",
+    "EighTridiagonalBatched",
     "default_options", "MrrrError", "last_stats", "library_path", "batched_layout",
 ]
 
@@ -203,9 +204,7 @@ def eigh_tridiagonal_batched(d_cat, e_cat, n_offsets, z_offsets=None, eigvals_on
     return (w_cat, Z_cat) if not eigvals_only else w_cat
 
 
-def eigh_tridiagonal_backward(w, Z, wbar=None, Zbar=None, gap_mask_rel=1e-8, count_masked=False):
-    """(dbar, ebar[, n_masked]) for cotangents (wbar, Zbar) of (w, Z) where Z
-    is the (n, n) tensor returned by eigh_tridiagonal (column-major view)."""
+def _backward_single(entry, w, Z, wbar, Zbar, gap_mask_rel, count_masked):
     w = _dev_f64(w, "w")
     n = w.numel()
     Z = _dev_f64(Z, "Z")
@@ -224,12 +223,26 @@ def eigh_tridiagonal_backward(w, Z, wbar=None, Zbar=None, gap_mask_rel=1e-8, cou
     ebar = w.new_empty(max(n - 1, 1))
     nm = ctypes.c_int64(0)
     h = _handle(w.device)
-    code = _lib.load().mrrr_dstemr_backward(h, n, _ptr(w), _ptr(Zc), max(n, 1), _ptr(wb), _ptr(Zb), max(n, 1),
-                                            float(gap_mask_rel), _ptr(dbar), _ptr(ebar),
-                                            ctypes.byref(nm) if count_masked else None)
-    _lib.check(code, "mrrr_dstemr_backward")
+    code = getattr(_lib.load(), entry)(h, n, _ptr(w), _ptr(Zc), max(n, 1), _ptr(wb), _ptr(Zb), max(n, 1),
+                                       float(gap_mask_rel), _ptr(dbar), _ptr(ebar),
+                                       ctypes.byref(nm) if count_masked else None)
+    _lib.check(code, entry)
     out = (dbar[:n], ebar[: max(n - 1, 0)])
     return out + (nm.value,) if count_masked else out
+
+
+def eigh_tridiagonal_backward(w, Z, wbar=None, Zbar=None, gap_mask_rel=1e-8, count_masked=False):
+    """(dbar, ebar[, n_masked]) for cotangents (wbar, Zbar) of (w, Z) where Z
+    is the (n, n) tensor returned by eigh_tridiagonal (column-major view)."""
+    return _backward_single("mrrr_dstemr_backward", w, Z, wbar, Zbar, gap_mask_rel, count_masked)
+
+
+def eigh_tridiagonal_backward_noalloc(w, Z, wbar=None, Zbar=None, gap_mask_rel=1e-8, count_masked=False):
+    """As eigh_tridiagonal_backward, through the C entry point that keeps its
+    work in the library's fixed per-GPU array (n <= 2048 with Zbar).  The
+    C call allocates nothing; this wrapper still makes the column-major copies
+    and the outputs as torch tensors."""
+    return _backward_single("mrrr_dstemr_backward_noalloc", w, Z, wbar, Zbar, gap_mask_rel, count_masked)
 
 
 def eigh_tridiagonal_backward_batched(w_cat, Z_cat, n_offsets, wbar_cat=None, Zbar_cat=None,

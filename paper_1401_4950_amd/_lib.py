@@ -18,7 +18,8 @@ STATUS = {
 EXPORTS = (
     "mrrr_create", "mrrr_destroy", "mrrr_set_stream", "mrrr_default_options",
     "mrrr_status_string", "mrrr_dstemr", "mrrr_dstemr_batched",
-    "mrrr_dstemr_backward", "mrrr_dstemr_backward_batched", "mrrr_diag_quotient",
+    "mrrr_dstemr_backward", "mrrr_dstemr_backward_batched", "mrrr_dstemr_backward_noalloc",
+    "mrrr_diag_quotient",
 )
 
 
@@ -94,6 +95,8 @@ def load():
     lib.mrrr_dstemr_backward.restype = i32
     lib.mrrr_dstemr_backward_batched.argtypes = [vp, i64, p64, vp, vp, p64, vp, vp, dbl, vp, vp, p64]
     lib.mrrr_dstemr_backward_batched.restype = i32
+    lib.mrrr_dstemr_backward_noalloc.argtypes = [vp, i64, vp, vp, i64, vp, vp, i64, dbl, vp, vp, p64]
+    lib.mrrr_dstemr_backward_noalloc.restype = i32
     lib.mrrr_diag_quotient.argtypes = [vp, i64, vp, vp, vp]
     lib.mrrr_diag_quotient.restype = i32
     _lib = lib

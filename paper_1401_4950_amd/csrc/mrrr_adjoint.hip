@@ -325,4 +325,90 @@ int adjoint_run(hipStream_t s, int64_t batch, const int64_t* noff, const int64_t
     return MRRR_OK;
 }
 
+
+// ------------------------------------------------- backward without allocation
+//
+// A fixed device array holds everything the backward keeps besides its
+// inputs and outputs: the problem record and the mask counter (first 512
+// bytes), M (n x n) and the partial sums (3 n ceil(n/32)), for n up to
+// MRRR_BACKWARD_NOALLOC_MAX_N.  Every call on one GPU uses that GPU's copy of
+// the array, so calls that overlap on one GPU race.  Host code never names the
+// array: it uses the address hipGetSymbolAddress returned for the device.
+
+constexpr int64_t kNaMaxN = MRRR_BACKWARD_NOALLOC_MAX_N;
+constexpr int64_t kNaHeader = 64;   // doubles: AdjProb at 0, counter at byte 256
+constexpr int64_t kNaDoubles = kNaHeader + kNaMaxN * kNaMaxN + 3 * kNaMaxN * ((kNaMaxN + 31) / 32);
+static_assert(sizeof(AdjProb) <= 256, "problem record must fit the header");
+
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+// Called once per device at handle creation, with that device current.
+int adjoint_scratch_address(void** ptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) {
+        *ptr = nullptr;
+        return MRRR_EHIP;
+    }
+    *ptr = p;
+    return MRRR_OK;
+}
+
+// The record and the cleared counter are written by a kernel (its argument
+// is copied at launch), so the call copies nothing from host memory.
+extern "C" __global__ void mrrr_adj_na_setup(AdjProb p, AdjProb* dst, unsigned long long* cnt) {
+    if (threadIdx.x == 0) {
+        *dst = p;
+        *cnt = 0ull;
+    }
+}
+
+extern "C" __global__ void mrrr_adj_na_zero(double* __restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+int adjoint_run_noalloc(hipStream_t s, void* scr, int64_t n, const double* w, const double* Z, int64_t ldz,
+                        const double* wbar, const double* Zbar, int64_t ldzbar, double gap_mask_rel,
+                        double* dbar, double* ebar, int64_t* n_masked_h) {
+    if (!scr) return MRRR_EHIP;
+    if (Zbar && n > kNaMaxN) return -2;
+    AdjProb pr{};
+    pr.n = n;
+    pr.ldz = ldz;
+    pr.ldzb = Zbar ? ldzbar : ldz;
+    pr.epad = 0;
+    AdjProb* dprob = static_cast<AdjProb*>(scr);
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(static_cast<char*>(scr) + 256);
+    double* Mb = static_cast<double*>(scr) + kNaHeader;
+    double* part = Mb + n * n;
+    const unsigned rows_blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(mrrr_adj_na_setup, dim3(1), dim3(64), 0, s, pr, dprob, cnt);
+    if (!Zbar) {
+        if (wbar) {
+            hipLaunchKernelGGL(mrrr_adj_values, dim3(rows_blocks, 1), dim3(256), 0, s, dprob, Z, wbar, dbar, ebar);
+        } else {
+            hipLaunchKernelGGL(mrrr_adj_na_zero, dim3(rows_blocks), dim3(256), 0, s, dbar, n);
+            if (n > 1)
+                hipLaunchKernelGGL(mrrr_adj_na_zero, dim3(rows_blocks), dim3(256), 0, s, ebar, n - 1);
+        }
+    } else {
+        hipLaunchKernelGGL(mrrr_adj_thresh, dim3(1), dim3(256), 0, s, dprob, w, gap_mask_rel);
+        const unsigned tiles = (unsigned)((n + kBM - 1) / kBM);
+        hipLaunchKernelGGL(mrrr_adj_form_m, dim3(tiles, tiles, 1), dim3(256), 0, s, dprob, w, Z, Zbar, wbar, Mb,
+                           cnt);
+        hipLaunchKernelGGL(mrrr_adj_reduce, dim3(tiles, tiles, 1), dim3(256), 0, s, dprob, Z, Mb, part);
+        hipLaunchKernelGGL(mrrr_adj_finish, dim3(rows_blocks, 1), dim3(256), 0, s, dprob, part, dbar, ebar);
+    }
+    if (hipGetLastError() != hipSuccess) return MRRR_EHIP;
+    if (n_masked_h) {
+        unsigned long long hc = 0;
+        if (Zbar) {
+            if (hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s) != hipSuccess) return MRRR_EHIP;
+            if (hipStreamSynchronize(s) != hipSuccess) return MRRR_EHIP;
+        }
+        *n_masked_h = (int64_t)hc;
+    }
+    return MRRR_OK;
+}
+
 }  // namespace mrrr

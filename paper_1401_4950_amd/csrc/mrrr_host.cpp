@@ -28,6 +28,10 @@ int adjoint_run(hipStream_t s, int64_t batch, const int64_t* n_offsets_h, const 
                 const double* w, const double* Z, const double* wbar, const double* Zbar,
                 double gap_mask_rel, double* dbar, double* ebar, int64_t* n_masked_h, int64_t ldz_single,
                 int64_t ldzbar_single, void* (*alloc)(void*, size_t), void* alloc_ctx);
+int adjoint_scratch_address(void** ptr);
+int adjoint_run_noalloc(hipStream_t s, void* scr, int64_t n, const double* w, const double* Z, int64_t ldz,
+                        const double* wbar, const double* Zbar, int64_t ldzbar, double gap_mask_rel,
+                        double* dbar, double* ebar, int64_t* n_masked_h);
 }  // namespace mrrr
 
 using namespace mrrr;
@@ -105,6 +109,7 @@ struct mrrr_handle_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evt0 = nullptr, evt1 = nullptr;
     mrrr_batched_plan_s* plan = nullptr;   // most recent batched plan
     DevBuf adj;                            // backward scratch
+    void* na_scratch = nullptr;            // this device's fixed backward scratch (no-allocation entry point)
 };
 
 extern "C" void mrrr_default_options(mrrr_options_t* o) {
@@ -160,6 +165,10 @@ extern "C" int mrrr_create(mrrr_handle_t* h, int device) {
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate > 0)
         H->wall_khz = (double)rate;
+    // the fixed scratch of the no-allocation backward: its address on this
+    // device, taken once here with the device current (a failure is reported
+    // by that entry point, the rest of the library does not need it)
+    if (adjoint_scratch_address(&H->na_scratch) != MRRR_OK) H->na_scratch = nullptr;
     int occ = 0;
     if (tree_occupancy(&occ) != hipSuccess || occ < 1) occ = 1;
     H->occ = occ;
@@ -662,6 +671,27 @@ extern "C" int mrrr_dstemr_backward(mrrr_handle_t h, int64_t n, const double* w,
     const int64_t noff[2] = {0, n};
     return adjoint_run(h->stream, 1, noff, nullptr, w, Z, wbar, Zbar, gap_mask_rel, dbar, ebar, n_masked, ldz,
                        ldzbar, adj_alloc, &h->adj);
+}
+
+extern "C" int mrrr_dstemr_backward_noalloc(mrrr_handle_t h, int64_t n, const double* w, const double* Z,
+                                            int64_t ldz, const double* wbar, const double* Zbar, int64_t ldzbar,
+                                            double gap_mask_rel, double* dbar, double* ebar, int64_t* n_masked) {
+    if (!h) return -1;
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return -2;
+    if (Zbar && n > MRRR_BACKWARD_NOALLOC_MAX_N) return -2;
+    if (n > 0 && !w) return -3;
+    if (n > 0 && !Z) return -4;
+    if (ldz < std::max<int64_t>(1, n)) return -5;
+    if (Zbar && ldzbar < std::max<int64_t>(1, n)) return -8;
+    if (!(gap_mask_rel >= 0.0)) return -9;
+    if (n > 0 && !dbar) return -10;
+    if (n > 1 && !ebar) return -11;
+    if (n_masked) *n_masked = 0;
+    if (n == 0) return MRRR_OK;
+    if (!h->na_scratch) return MRRR_EHIP;
+    if (hipSetDevice(h->device) != hipSuccess) return MRRR_EHIP;
+    return adjoint_run_noalloc(h->stream, h->na_scratch, n, w, Z, ldz, wbar, Zbar, ldzbar, gap_mask_rel, dbar, ebar,
+                               n_masked);
 }
 
 extern "C" int mrrr_dstemr_backward_batched(mrrr_handle_t h, int64_t batch, const int64_t* n_offsets,
