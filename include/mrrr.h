@@ -50,7 +50,7 @@ typedef enum {
     MRRR_ENOMEM = 2,     /* device allocation or a work-queue capacity failed */
     MRRR_ENOCONV = 3,    /* an eigenvalue failed to converge */
     MRRR_EHIP = 4,       /* a HIP runtime call failed */
-    MRRR_ENOTIMPL = 5,   /* a valid but unsupported request */
+                         /* 5 is not used */
     MRRR_ETIMEOUT = 6,   /* the device watchdog stopped the solve */
     MRRR_EINTERNAL = 7   /* an internal consistency check failed */
 } mrrr_status_t;
@@ -187,10 +187,60 @@ const char *mrrr_status_string(int status);
  *            fills it.
  * The call always waits for the device to finish (it must read back the
  * device status word, so that a failure is reported, never hidden).
- * Errors: negative argument index, MRRR_ENOMEM, MRRR_ETIMEOUT,
- * MRRR_ENOTIMPL (INDEX range on a matrix that splits into several blocks),
- * MRRR_EHIP.  MRRR_WARN_UNVERIFIED still fills all outputs. */
+ * An INDEX range over a matrix that splits into several blocks selects by
+ * rank in the direct sum of the blocks; eigenvalues of different blocks that
+ * agree to working accuracy are ranked in block order.
+ * Errors: negative argument index, MRRR_ENOMEM, MRRR_ETIMEOUT, MRRR_EHIP.
+ * MRRR_WARN_UNVERIFIED still fills all outputs. */
 int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double *d, const double *e,
+                int range, double vl, double vu, int64_t il, int64_t iu,
+                const mrrr_options_t *opts, int64_t *m, double *w, double *Z,
+                int64_t ldz, mrrr_stats_t *stats);
+
+/* Fills *o with the defaults of the single/double form (Sec. 5.1.1 and the
+ * single/double settings of Sec. 5.2.1): gaptol 1e-5, rtol_class 1e-7
+ * (1e-2 gaptol), perturb_xi 2^29 (the root's data perturbed by up to
+ * eps_single = 2^-24 relative); everything else as mrrr_default_options. */
+void mrrr_default_options_mixed(mrrr_options_t *o);
+
+/* mrrr_sstemr: the mixed-precision MRRR of Ch. 5 for single-precision data
+ * (single/double): input and output in FP32, every step inside in FP64.
+ * The arguments mean what they mean for mrrr_dstemr, with float in place of
+ * double for d, e, vl, vu, w and Z (device pointers, Z column-major with
+ * ldz >= max(1, n)); opts NULL means mrrr_default_options_mixed.  The data
+ * are widened exactly, the matrix splits where |beta_i| <= eps_s sqrt(n)
+ * ||T|| (eps_s = 2^-24), the Rayleigh-quotient iteration stops once the local
+ * residual is below eps_s sqrt(n) times the gap, and the results are rounded
+ * to nearest FP32 as they are written.  The goal is residual and
+ * orthogonality of order eps_s sqrt(n).
+ * Workspace: the handle keeps FP64 copies of d, e, w and of Z (n x m
+ * doubles), grown on demand.
+ * Errors: as mrrr_dstemr. */
+int mrrr_sstemr(mrrr_handle_t h, int64_t n, const float *d, const float *e,
+                int range, float vl, float vu, int64_t il, int64_t iu,
+                const mrrr_options_t *opts, int64_t *m, float *w, float *Z,
+                int64_t ldz, mrrr_stats_t *stats);
+
+/* mrrr_dsyevr: eigenpairs of a dense real symmetric matrix A by the three
+ * stages of Sec. 2.3.2 -- reduction to tridiagonal form A = Q T Q^T, MRRR on
+ * T (as mrrr_dstemr), back-transformation Z := Q Z_T.  The reduction and the
+ * back-transformation are the library routines of rocSOLVER (Householder
+ * tridiagonalisation of the lower triangle, and the application of its
+ * reflectors).
+ *   A        device, n x n column-major with leading dimension lda >= max(1, n);
+ *            only the lower triangle is read; A is not modified (the handle
+ *            keeps a reduced copy).
+ *   range .. ldz, stats: as mrrr_dstemr, at the same argument positions (A
+ *            and lda take the places of d and e).  The sign convention is
+ *            applied to the vectors of A.  stats describe the tridiagonal
+ *            solve.
+ * Workspace: the handle keeps n^2 + 3n doubles and a rocBLAS handle, both
+ * created on first use; rocSOLVER allocates its own scratch.
+ * The call synchronises the handle's stream before returning.
+ * Errors: negative argument index, MRRR_ENOMEM, MRRR_EHIP (including a
+ * failure of the reduction or the back-transformation), and those of
+ * mrrr_dstemr. */
+int mrrr_dsyevr(mrrr_handle_t h, int64_t n, const double *A, int64_t lda,
                 int range, double vl, double vu, int64_t il, int64_t iu,
                 const mrrr_options_t *opts, int64_t *m, double *w, double *Z,
                 int64_t ldz, mrrr_stats_t *stats);

@@ -26,7 +26,7 @@ from ._lib import MrrrError, Options, Stats, default_options  # noqa: F401
 __all__ = [
     "eigh_tridiagonal", "eigh_tridiagonal_batched", "eigh_tridiagonal_backward",
     "eigh_tridiagonal_backward_batched", "eigh_tridiagonal_backward_noalloc", "EighTridiagonal",
-    "EighTridiagonalBatched",
+    "EighTridiagonalBatched", "eigh_symmetric",
     "default_options", "MrrrError", "last_stats", "library_path", "batched_layout",
 ]
 
@@ -117,16 +117,32 @@ def _options(options, jobz):
     return o
 
 
+def _dev_real(x, name, dtype):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} like d")
+    return x.contiguous()
+
+
 def eigh_tridiagonal(d, e, select="a", select_range=None, eigvals_only=False, options=None):
     """Eigenpairs of tridiag(e, d, e) by MRRR on the GPU.
 
     select: 'a' (all), 'v' (values in the half-open [vl, vu)), 'i' (indices
     il..iu, 1-based inclusive).  Returns (w, Z) with Z n x m column-major as
     a torch tensor of shape (n, m) -- or w alone when eigvals_only.
+
+    float64 d, e: mrrr_dstemr.  float32 d, e: mrrr_sstemr, the
+    single/double form (FP32 in and out, FP64 inside; its options default to
+    mrrr_default_options_mixed).
     """
-    d = _dev_f64(d, "d")
+    if not isinstance(d, torch.Tensor) or d.dtype not in (torch.float64, torch.float32):
+        raise TypeError("d must be a float64 or float32 CUDA tensor")
+    mixed = d.dtype == torch.float32
+    dt = d.dtype
+    d = _dev_real(d, "d", dt)
     n = d.numel()
-    e = _dev_f64(e, "e") if n > 1 else d.new_zeros(1)
+    e = _dev_real(e, "e", dt) if n > 1 else d.new_zeros(1)
     if n > 1 and e.numel() != n - 1:
         raise ValueError("e must have n-1 entries")
     rng = {"a": 0, "all": 0, "v": 1, "value": 1, "i": 2, "index": 2}[select]
@@ -137,17 +153,58 @@ def eigh_tridiagonal(d, e, select="a", select_range=None, eigvals_only=False, op
     elif rng == 2:
         il, iu = (int(x) for x in select_range)
     ncols = n if rng != 2 else max(iu - il + 1, 0)
-    o = _options(options, not eigvals_only)
+    if isinstance(options, Options):
+        o = options
+    else:
+        o = default_options(mixed=mixed, **(options or {}))
+    o.jobz = 0 if eigvals_only else 1
     w = d.new_empty(max(n, 1))
     # column-major n x ncols: a (ncols, n) row-major buffer, transposed view
     Zbuf = d.new_empty((max(ncols, 1), max(n, 1))) if not eigvals_only else None
     m = ctypes.c_int64(0)
     st = Stats()
     h = _handle(d.device)
-    code = _lib.load().mrrr_dstemr(h, n, _ptr(d), _ptr(e), rng, vl, vu, il, iu, ctypes.byref(o),
-                                   ctypes.byref(m), _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(st))
+    entry = "mrrr_sstemr" if mixed else "mrrr_dstemr"
+    code = getattr(_lib.load(), entry)(h, n, _ptr(d), _ptr(e), rng, vl, vu, il, iu, ctypes.byref(o),
+                                       ctypes.byref(m), _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(st))
     _tls.stats = st
-    _lib.check(code, "mrrr_dstemr")
+    _lib.check(code, entry)
+    k = m.value
+    w = w[:k]
+    if eigvals_only:
+        return w
+    return w, Zbuf[:k].t()
+
+
+def eigh_symmetric(A, select="a", select_range=None, eigvals_only=False, options=None):
+    """Eigenpairs of a dense real symmetric matrix A (n x n float64 CUDA
+    tensor) through mrrr_dsyevr: reduction to tridiagonal form, MRRR,
+    back-transformation.  Only one triangle is read (A must be symmetric);
+    select and the outputs are as for eigh_tridiagonal."""
+    if not isinstance(A, torch.Tensor) or not A.is_cuda or A.dtype != torch.float64:
+        raise TypeError("A must be a float64 CUDA (HIP) tensor")
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError(f"A must be square, got {tuple(A.shape)}")
+    A = A.contiguous()            # row-major storage of a symmetric matrix = its column-major storage
+    n = A.shape[0]
+    rng = {"a": 0, "all": 0, "v": 1, "value": 1, "i": 2, "index": 2}[select]
+    vl = vu = 0.0
+    il = iu = 0
+    if rng == 1:
+        vl, vu = (float(x) for x in select_range)
+    elif rng == 2:
+        il, iu = (int(x) for x in select_range)
+    ncols = n if rng != 2 else max(iu - il + 1, 0)
+    o = _options(options, not eigvals_only)
+    w = A.new_empty(max(n, 1))
+    Zbuf = A.new_empty((max(ncols, 1), max(n, 1))) if not eigvals_only else None
+    m = ctypes.c_int64(0)
+    st = Stats()
+    h = _handle(A.device)
+    code = _lib.load().mrrr_dsyevr(h, n, _ptr(A), max(n, 1), rng, vl, vu, il, iu, ctypes.byref(o), ctypes.byref(m),
+                                   _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(st))
+    _tls.stats = st
+    _lib.check(code, "mrrr_dsyevr")
     k = m.value
     w = w[:k]
     if eigvals_only:

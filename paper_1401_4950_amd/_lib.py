@@ -11,13 +11,14 @@ RANGE_ALL, RANGE_VALUE, RANGE_INDEX = 0, 1, 2
 
 STATUS = {
     0: "MRRR_OK", 1: "MRRR_WARN_UNVERIFIED", 2: "MRRR_ENOMEM", 3: "MRRR_ENOCONV",
-    4: "MRRR_EHIP", 5: "MRRR_ENOTIMPL", 6: "MRRR_ETIMEOUT", 7: "MRRR_EINTERNAL",
+    4: "MRRR_EHIP", 6: "MRRR_ETIMEOUT", 7: "MRRR_EINTERNAL",
 }
 
 #: every symbol include/mrrr.h declares
 EXPORTS = (
     "mrrr_create", "mrrr_destroy", "mrrr_set_stream", "mrrr_default_options",
-    "mrrr_status_string", "mrrr_dstemr", "mrrr_dstemr_batched",
+    "mrrr_status_string", "mrrr_dstemr", "mrrr_dstemr_batched", "mrrr_default_options_mixed",
+    "mrrr_sstemr", "mrrr_dsyevr",
     "mrrr_dstemr_backward", "mrrr_dstemr_backward_batched", "mrrr_dstemr_backward_noalloc",
     "mrrr_diag_quotient",
 )
@@ -88,6 +89,14 @@ def load():
     lib.mrrr_dstemr.argtypes = [vp, i64, vp, vp, i32, dbl, dbl, i64, i64, ctypes.POINTER(Options),
                                 p64, vp, vp, i64, ctypes.POINTER(Stats)]
     lib.mrrr_dstemr.restype = i32
+    lib.mrrr_default_options_mixed.argtypes = [ctypes.POINTER(Options)]
+    lib.mrrr_default_options_mixed.restype = None
+    lib.mrrr_sstemr.argtypes = [vp, i64, vp, vp, i32, ctypes.c_float, ctypes.c_float, i64, i64,
+                                ctypes.POINTER(Options), p64, vp, vp, i64, ctypes.POINTER(Stats)]
+    lib.mrrr_sstemr.restype = i32
+    lib.mrrr_dsyevr.argtypes = [vp, i64, vp, i64, i32, dbl, dbl, i64, i64, ctypes.POINTER(Options), p64, vp, vp,
+                                i64, ctypes.POINTER(Stats)]
+    lib.mrrr_dsyevr.restype = i32
     lib.mrrr_dstemr_batched.argtypes = [vp, i64, p64, vp, vp, p64, ctypes.POINTER(Options), vp, vp,
                                         ctypes.POINTER(Stats)]
     lib.mrrr_dstemr_batched.restype = i32
@@ -103,9 +112,11 @@ def load():
     return lib
 
 
-def default_options(**overrides) -> Options:
+def default_options(mixed: bool = False, **overrides) -> Options:
+    """The library's default options (mixed=True: those of the single/double
+    form), with the given fields overridden."""
     o = Options()
-    load().mrrr_default_options(ctypes.byref(o))
+    (load().mrrr_default_options_mixed if mixed else load().mrrr_default_options)(ctypes.byref(o))
     for k, v in overrides.items():
         if not hasattr(o, k):
             raise KeyError(k)

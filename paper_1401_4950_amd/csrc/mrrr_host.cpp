@@ -1,6 +1,8 @@
 // Host runtime behind include/mrrr.h: handle, workspace, argument checks,
 // launch sequence, status read-back, batched plans with hipGraph replay.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <cmath>
@@ -24,6 +26,9 @@ hipError_t launch_sign(const Params& P, int64_t ncols_total, hipStream_t s);
 hipError_t launch_check(const Params& P, hipStream_t s);
 hipError_t tree_occupancy(int* blocks_per_cu);
 hipError_t launch_quot(const double* a, const double* b, double* q, int64_t n, hipStream_t s);
+hipError_t launch_widen(const float* x, double* y, int64_t n, hipStream_t s);
+hipError_t launch_narrow(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int64_t cols,
+                         hipStream_t s);
 int adjoint_run(hipStream_t s, int64_t batch, const int64_t* n_offsets_h, const int64_t* z_offsets_h,
                 const double* w, const double* Z, const double* wbar, const double* Zbar,
                 double gap_mask_rel, double* dbar, double* ebar, int64_t* n_masked_h, int64_t ldz_single,
@@ -110,6 +115,9 @@ struct mrrr_handle_s {
     mrrr_batched_plan_s* plan = nullptr;   // most recent batched plan
     DevBuf adj;                            // backward scratch
     void* na_scratch = nullptr;            // this device's fixed backward scratch (no-allocation entry point)
+    DevBuf mixed;                          // single/double form: FP64 copies of d, e, w, Z
+    DevBuf dense;                          // dense driver: copy of A (reflectors), d, e, tau
+    rocblas_handle rb = nullptr;           // dense driver: reduction and back-transformation
 };
 
 extern "C" void mrrr_default_options(mrrr_options_t* o) {
@@ -143,7 +151,6 @@ extern "C" const char* mrrr_status_string(int s) {
         case MRRR_ENOMEM: return "out of device memory or work-queue capacity";
         case MRRR_ENOCONV: return "an eigenvalue did not converge";
         case MRRR_EHIP: return "HIP runtime error";
-        case MRRR_ENOTIMPL: return "not implemented for this input";
         case MRRR_ETIMEOUT: return "device watchdog expired";
         case MRRR_EINTERNAL: return "internal consistency check failed";
         default: return "unknown status";
@@ -190,6 +197,9 @@ extern "C" int mrrr_destroy(mrrr_handle_t h) {
     if (h->plan) { h->plan->release(); delete h->plan; }
     h->ws.release();
     h->adj.release();
+    h->mixed.release();
+    h->dense.release();
+    if (h->rb) (void)rocblas_destroy_handle(h->rb);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     if (h->evt0) (void)hipEventDestroy(h->evt0);
@@ -211,7 +221,6 @@ int map_device_error(int code) {
         case kErrNone: return MRRR_OK;
         case kErrNoMem: return MRRR_ENOMEM;
         case kErrNoConv: return MRRR_ENOCONV;
-        case kErrNotImpl: return MRRR_ENOTIMPL;
         case kErrTimeout: return MRRR_ETIMEOUT;
         case kErrBadD: return -3;
         case kErrBadE: return -4;
@@ -278,7 +287,7 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     return hipSuccess;
 }
 
-void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int workers) {
+void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int workers, double io_eps = 0.0) {
     P.jobz = o.jobz ? 1 : 0;
     P.gaptol = o.gaptol;
     P.rtol = o.rtol_class;
@@ -294,12 +303,13 @@ void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int worker
     P.trace = (o.trace && o.trace_cap > 0) ? static_cast<TraceRec*>(o.trace) : nullptr;
     P.trace_cap = P.trace ? o.trace_cap : 0;
     P.check_tol = o.check_tol;
+    P.io_eps = io_eps;
 }
 
 int check_options(const mrrr_options_t& o) {
     if (!(o.gaptol > 0.0 && o.gaptol < 1.0)) return 1;
     if (!(o.rtol_class > 0.0 && o.rtol_class < 1.0)) return 1;
-    if (!(o.perturb_xi >= 0.0 && o.perturb_xi < 1e6)) return 1;
+    if (!(o.perturb_xi >= 0.0 && o.perturb_xi <= 0x1p30)) return 1;
     if (o.max_rqi < 0 || o.max_shift_tries < 1 || o.max_depth < 1) return 1;
     if (!(o.timeout_s > 0.0)) return 1;
     if (o.trace_cap < 0) return 1;
@@ -404,9 +414,12 @@ int workers_for(mrrr_handle_t h, const mrrr_options_t& o) {
 
 }  // namespace
 
-extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const double* e, int range,
-                           double vl, double vu, int64_t il, int64_t iu, const mrrr_options_t* opts,
-                           int64_t* m, double* w, double* Z, int64_t ldz, mrrr_stats_t* stats) {
+namespace {
+
+// Arguments of one single-matrix solve, validated by the caller's entry point.
+int check_single(mrrr_handle_t h, int64_t n, const void* d, const void* e, int range, double vl, double vu,
+                 int64_t il, int64_t iu, const mrrr_options_t& o, const int64_t* m, const void* w, const void* Z,
+                 int64_t ldz) {
     if (!h) return -1;
     if (n < 0 || n > (int64_t)INT32_MAX / 2) return -2;
     if (n > 0 && !d) return -3;
@@ -415,18 +428,18 @@ extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const do
     if (range == MRRR_RANGE_VALUE && !(std::isfinite(vl) && std::isfinite(vu) && vl < vu)) return -7;
     if (range == MRRR_RANGE_INDEX && (il < 1 || il > n + 1)) return -8;
     if (range == MRRR_RANGE_INDEX && (iu < il - 1 || iu > n)) return -9;
-    mrrr_options_t o;
-    mrrr_default_options(&o);
-    if (opts) o = *opts;
     if (check_options(o)) return -10;
     if (!m) return -11;
     if (n > 0 && !w) return -12;
     if (o.jobz && n > 0 && !Z) return -13;
     if (o.jobz && ldz < std::max<int64_t>(1, n)) return -14;
-    *m = 0;
-    if (stats) std::memset(stats, 0, sizeof(*stats));
-    if (n == 0 || (range == MRRR_RANGE_INDEX && iu < il)) return MRRR_OK;
-    if (hipSetDevice(h->device) != hipSuccess) return MRRR_EHIP;
+    return MRRR_OK;
+}
+
+// The solve of one matrix on device data already in FP64 (arguments checked).
+int solve_single(mrrr_handle_t h, int64_t n, const double* d, const double* e, int range, double vl, double vu,
+                 int64_t il, int64_t iu, const mrrr_options_t& o, double io_eps, int64_t* m, double* w, double* Z,
+                 int64_t ldz, mrrr_stats_t* stats) {
 
     Problem pr{};
     pr.row0 = 0;
@@ -442,13 +455,13 @@ extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const do
     apply_tune(pr, o, nullptr, 0);
     int64_t kwork = n;
     pr.ck_base = 0;
-    pr.ck_slot0 = 0;
     pr.ck_stride = n;
     if (range == MRRR_RANGE_INDEX) {
+        // work: the wanted indices and a guard on each side; checkpoint
+        // columns: one per output column
         const int64_t k0 = std::max<int64_t>(il - 1, 1), k1 = std::min<int64_t>(iu + 1, n);
-        pr.ck_slot0 = k0 - 1;
-        pr.ck_stride = k1 - k0 + 1;
-        kwork = pr.ck_stride;
+        kwork = k1 - k0 + 1;
+        pr.ck_stride = iu - il + 1;
     }
     const int workers = workers_for(h, o);
     int status = MRRR_OK;
@@ -463,7 +476,7 @@ extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const do
         P.Z = Z;
         P.nprob = 1;
         if (prepare(h->ws, sz, P) != hipSuccess) return MRRR_ENOMEM;
-        set_options(P, o, h->wall_khz, workers);
+        set_options(P, o, h->wall_khz, workers, io_eps);
         if (hipMemcpyAsync(P.probs, &pr, sizeof(Problem), hipMemcpyHostToDevice, h->stream) != hipSuccess)
             return MRRR_EHIP;
         if (hipEventRecord(h->ev0, h->stream) != hipSuccess) return MRRR_EHIP;
@@ -489,6 +502,130 @@ extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const do
     return status;
 }
 
+}  // namespace
+
+extern "C" int mrrr_dstemr(mrrr_handle_t h, int64_t n, const double* d, const double* e, int range,
+                           double vl, double vu, int64_t il, int64_t iu, const mrrr_options_t* opts,
+                           int64_t* m, double* w, double* Z, int64_t ldz, mrrr_stats_t* stats) {
+    mrrr_options_t o;
+    mrrr_default_options(&o);
+    if (opts) o = *opts;
+    const int bad = check_single(h, n, d, e, range, vl, vu, il, iu, o, m, w, Z, ldz);
+    if (bad != MRRR_OK) return bad;
+    *m = 0;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (n == 0 || (range == MRRR_RANGE_INDEX && iu < il)) return MRRR_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return MRRR_EHIP;
+    return solve_single(h, n, d, e, range, vl, vu, il, iu, o, 0.0, m, w, Z, ldz, stats);
+}
+
+extern "C" void mrrr_default_options_mixed(mrrr_options_t* o) {
+    if (!o) return;
+    mrrr_default_options(o);
+    o->gaptol = 1e-5;            // Sec. 5.2.1: fixed at 1e-5 for single/double
+    o->rtol_class = 1e-7;        // 1e-2 gaptol, for the first bisection and the refinements
+    o->perturb_xi = 0x1p29;      // xi = eps_single = 2^-24 = 2^29 eps_double
+}
+
+extern "C" int mrrr_sstemr(mrrr_handle_t h, int64_t n, const float* d, const float* e, int range, float vl,
+                           float vu, int64_t il, int64_t iu, const mrrr_options_t* opts, int64_t* m, float* w,
+                           float* Z, int64_t ldz, mrrr_stats_t* stats) {
+    mrrr_options_t o;
+    mrrr_default_options_mixed(&o);
+    if (opts) o = *opts;
+    const int bad = check_single(h, n, d, e, range, (double)vl, (double)vu, il, iu, o, m, w, Z, ldz);
+    if (bad != MRRR_OK) return bad;
+    *m = 0;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (n == 0 || (range == MRRR_RANGE_INDEX && iu < il)) return MRRR_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return MRRR_EHIP;
+    // FP64 working copies: d, e (n each), w (n), Z (n x kmax, ld n)
+    const int64_t kmax = (range == MRRR_RANGE_INDEX) ? iu - il + 1 : n;
+    const size_t need = sizeof(double) * (3 * (size_t)n + (o.jobz ? (size_t)n * (size_t)kmax : 0));
+    if (h->mixed.ensure(need) != hipSuccess) return MRRR_ENOMEM;
+    double* d64 = h->mixed.as<double>();
+    double* e64 = d64 + n;
+    double* w64 = e64 + n;
+    double* Z64 = o.jobz ? w64 + n : nullptr;
+    if (launch_widen(d, d64, n, h->stream) != hipSuccess) return MRRR_EHIP;
+    if (n > 1 && launch_widen(e, e64, n - 1, h->stream) != hipSuccess) return MRRR_EHIP;
+    const int st = solve_single(h, n, d64, e64, range, (double)vl, (double)vu, il, iu, o, 0x1p-24, m, w64, Z64,
+                                std::max<int64_t>(n, 1), stats);
+    if (st != MRRR_OK && st != MRRR_WARN_UNVERIFIED) return st;
+    const int64_t mm = *m;
+    if (mm > 0) {
+        if (launch_narrow(w64, 1, w, 1, mm, 1, h->stream) != hipSuccess) return MRRR_EHIP;
+        if (o.jobz && launch_narrow(Z64, n, Z, ldz, n, mm, h->stream) != hipSuccess) return MRRR_EHIP;
+    }
+    return st;
+}
+
+// ------------------------------------------------------------ dense driver
+
+extern "C" int mrrr_dsyevr(mrrr_handle_t h, int64_t n, const double* A, int64_t lda, int range, double vl, double vu,
+                           int64_t il, int64_t iu, const mrrr_options_t* opts, int64_t* m, double* w, double* Z,
+                           int64_t ldz, mrrr_stats_t* stats) {
+    if (!h) return -1;
+    if (n < 0 || n > (int64_t)INT32_MAX / 2) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    mrrr_options_t o;
+    mrrr_default_options(&o);
+    if (opts) o = *opts;
+    // A and lda take the argument positions of d and e; the others are
+    // checked as mrrr_dstemr checks them
+    const int bad = check_single(h, n, A, A, range, vl, vu, il, iu, o, m, w, Z, ldz);
+    if (bad != MRRR_OK) return bad;
+    *m = 0;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (n == 0 || (range == MRRR_RANGE_INDEX && iu < il)) return MRRR_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return MRRR_EHIP;
+    if (!h->rb && rocblas_create_handle(&h->rb) != rocblas_status_success) {
+        h->rb = nullptr;
+        return MRRR_EHIP;
+    }
+    if (rocblas_set_stream(h->rb, h->stream) != rocblas_status_success) return MRRR_EHIP;
+    // workspace: the reduced matrix (its lower triangle holds the Householder
+    // vectors of Q), the tridiagonal's d and e, and the reflectors' scalars
+    const size_t nn = (size_t)n * (size_t)n;
+    if (h->dense.ensure(sizeof(double) * (nn + 3 * (size_t)n)) != hipSuccess) return MRRR_ENOMEM;
+    double* Aw = h->dense.as<double>();
+    double* dd = Aw + nn;
+    double* ee = dd + n;
+    double* tau = ee + n;
+    if (hipMemcpy2DAsync(Aw, sizeof(double) * (size_t)n, A, sizeof(double) * (size_t)lda, sizeof(double) * (size_t)n,
+                         (size_t)n, hipMemcpyDeviceToDevice, h->stream) != hipSuccess)
+        return MRRR_EHIP;
+    // 1. A = Q T Q^T (Householder reduction of the lower triangle)
+    if (rocsolver_dsytrd(h->rb, rocblas_fill_lower, (rocblas_int)n, Aw, (rocblas_int)n, dd, ee, tau) !=
+        rocblas_status_success)
+        return MRRR_EHIP;
+    // 2. eigenpairs of T by MRRR (the sign convention waits for the vectors of A)
+    mrrr_options_t ot = o;
+    ot.sign_convention = 0;
+    const int st = solve_single(h, n, dd, ee, range, vl, vu, il, iu, ot, 0.0, m, w, Z, ldz, stats);
+    if (st != MRRR_OK && st != MRRR_WARN_UNVERIFIED) return st;
+    const int64_t mm = *m;
+    if (o.jobz && mm > 0) {
+        // 3. Z := Q Z
+        if (rocsolver_dormtr(h->rb, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, (rocblas_int)n,
+                             (rocblas_int)mm, Aw, (rocblas_int)n, tau, Z, (rocblas_int)ldz) != rocblas_status_success)
+            return MRRR_EHIP;
+        if (o.sign_convention) {
+            // the problem record of the solve still describes Z (n rows, mm
+            // columns, leading dimension ldz)
+            Params P{};
+            P.probs = h->ws.probs.as<Problem>();
+            P.nprob = 1;
+            P.Z = Z;
+            P.ctl = h->ws.ctl.as<Ctl>();
+            if (launch_sign(P, mm, h->stream) != hipSuccess) return MRRR_EHIP;
+        }
+    }
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return MRRR_EHIP;
+    return st;
+}
+
 // ------------------------------------------------------------------ batched
 
 namespace {
@@ -512,7 +649,6 @@ int build_plan(mrrr_handle_t h, mrrr_batched_plan_s* pl) {
         pr.range = MRRR_RANGE_ALL;
         apply_tune(pr, pl->opts, pl->tune.empty() ? nullptr : pl->tune.data(), b);
         pr.ck_base = ck;
-        pr.ck_slot0 = pl->noff[b];
         pr.ck_stride = nb;
         ck += pl->opts.jobz ? kCkSlots * ((nb + kCkb - 1) / kCkb) * nb : 0;
         zpack += nb * nb;

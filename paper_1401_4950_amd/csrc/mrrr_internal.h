@@ -33,7 +33,7 @@ enum TaskType : int32_t {
 enum RefineMode : int32_t { kModeClass = 0, kModeFull = 1 };
 
 enum ErrCode : int32_t {
-    kErrNone = 0, kErrNoMem = 2, kErrNoConv = 3, kErrNotImpl = 5,
+    kErrNone = 0, kErrNoMem = 2, kErrNoConv = 3,
     kErrTimeout = 6, kErrInternal = 7,
     kErrBadD = 100, kErrBadE = 101   // non-finite input data
 };
@@ -58,8 +58,7 @@ struct Problem {
     int64_t m;        // device: number of eigenpairs returned
     double bnorm;     // device: Gershgorin bound of the whole problem
     int64_t ck_base;  // checkpoint region (doubles) of this problem
-    int64_t ck_slot0; // first slot with a checkpoint column
-    int64_t ck_stride;
+    int64_t ck_stride;  // checkpoint columns: one per output column
     int32_t flags;    // device: bit0 several blocks; bit1 columns to permute
     int16_t lanes;    // most multisection lanes per eigenvalue (power of two)
     int16_t bundle;   // singletons per S-task
@@ -187,6 +186,8 @@ struct Params {
     CheckRec* chk;        // clusters checked after the tree (see CheckRec)
     int64_t chk_cap;
     double check_tol;     // correct when max |Z^T Z - I| > check_tol n eps
+    double io_eps;        // unit roundoff of the caller's data format when it is
+                          // coarser than FP64 (single/double: 2^-24), else 0
 };
 
 }  // namespace mrrr

@@ -2805,9 +2805,12 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
     int vf = P.vflag[slot];
     double lam = lo + 0.5 * (hi - lo);
     CkPtr ck;
-    ck.base = P.ck + pr.ck_base + (slot - pr.ck_slot0);
+    ck.base = P.ck + pr.ck_base + (blk.col0 + (j - blk.w0));   // one column per output column
     ck.stride = pr.ck_stride;
-    const double tol1 = (double)n * kEps, tol2 = 2.0 * kEps;
+    // tol1: the local residual may stop at n eps gap in FP64; with data in a
+    // coarser format (unit roundoff eps_x) the orthogonality goal is
+    // eps_x sqrt(n), and the iteration stops at eps_x sqrt(n) gap (Sec. 5.1.1)
+    const double tol1 = (P.io_eps > 0.0) ? P.io_eps * sqrt((double)n) : (double)n * kEps, tol2 = 2.0 * kEps;
     // Alg. 4.3: Rayleigh-quotient steps while the correction improves the
     // eigenvalue -- right sign, inside the bracket, and at most half the
     // previous correction (a correction that stops shrinking is at the
@@ -2895,12 +2898,18 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
         }
         const double scale = 1.0 / sqrt(nrm2);
         solve_vector(S, D, L, n, lam, act, r, scale, ck, zcol, true, tg, steps);
-        if (act && (pr.flags & 1)) {
-            // several blocks: the rest of the column is zero
-            double* zc = P.Z + pr.zoff + col * pr.ldz;
+        if (pr.flags & 1) {
+            // several blocks: the rest of each column is zero, written column
+            // by column with the wave's lanes on consecutive rows
             const int64_t r0 = blk.row0 - pr.row0;
-            for (int64_t i = 0; i < r0; ++i) zc[i] = 0.0;
-            for (int64_t i = r0 + n; i < pr.n; ++i) zc[i] = 0.0;
+            uint64_t am = __ballot(act);
+            while (am) {
+                const int c = __ffsll((unsigned long long)am) - 1;
+                am &= am - 1ull;
+                double* zc = P.Z + pr.zoff + __shfl(col, c) * pr.ldz;
+                for (int64_t i = l; i < r0; i += kWave) zc[i] = 0.0;
+                for (int64_t i = r0 + n + l; i < pr.n; i += kWave) zc[i] = 0.0;
+            }
         }
     }
     if (act) P.w[pr.woff + col] = (nd.sigma + lam) * pr.tscale_inv;
@@ -3072,7 +3081,9 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
         return;
     }
     const double bnorm = fmax(fabs(gl), fabs(gu));
-    const double tol = kEps * sqrt((double)n) * bnorm;
+    // splitting (Sec. 3.2.1): |beta_i| <= eps sqrt(n) ||T||, with eps the
+    // unit roundoff of the caller's data format (Sec. 5.1.1 for single/double)
+    const double tol = (P.io_eps > 0.0 ? P.io_eps : kEps) * sqrt((double)n) * bnorm;
     // The tree works on 2^-k T with the Gershgorin bound in [1/2, 1): a
     // power of two changes no rounding, keeps squares of the entries and the
     // products of the division-free Sturm counts away from overflow and
@@ -3123,7 +3134,57 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
     // index ranges per block
     int64_t m = 0;
     int err = 0;
-    if (pr->range == 2 && nb > 1) err = kErrNotImpl;
+    // An index range over several blocks (Sec. 3.2.1): the il-th and iu-th
+    // eigenvalues of the direct sum are bracketed to full accuracy by
+    // multisection on the Sturm count of T with the split entries zero (the
+    // sum of the blocks' counts; lanes 0-31 for il, 32-63 for iu).  A block
+    // then keeps its eigenvalues above the il bracket and below the iu
+    // bracket; of the ones inside a bracket (equal to working accuracy) the
+    // lower blocks' come first, as in a stable merge by value.
+    const bool split_index = (pr->range == 2 && nb > 1);
+    double ta[2] = {0.0, 0.0}, tb[2] = {0.0, 0.0};   // brackets [a, b) of the two targets (scaled)
+    int64_t na[2] = {0, 0};                           // N(a) of each target
+    int64_t quota[2] = {0, 0};
+    if (split_index) {
+        const double slack = (2.0 * (double)n + 10.0) * bnorm * kEps;
+        const int t = l >> 5, j = l & 31;
+        const int64_t kt = t ? pr->iu : pr->il;
+        double a = (gl - slack) * tsc, bb = (gu + slack) * tsc;
+        int64_t ca = 0;
+        for (int pass = 0; pass < 2200; ++pass) {
+            const double wid = bb - a;
+            const bool done = !(wid > 2.0 * kEps * fmax(fabs(a), fabs(bb))) || !(a + 0.5 * wid > a && a + 0.5 * wid < bb);
+            if (__ballot(!done) == 0ull) break;
+            const double x = done ? a : a + wid * ((double)(j + 1) / 33.0);
+            int64_t c = 0;
+            for (int q = 0; q < nb; ++q) c += negcount_T(S, P.d + B[q].row0, P.e + B[q].row0, B[q].n, tsc, x);
+            // new bracket of this half: the highest point with N < k, the
+            // lowest with N >= k (points increase with the lane)
+            const bool below = !done && c < kt && x > a;
+            const bool above = !done && c >= kt && x < bb;
+            double na_x = below ? x : -__builtin_inf();
+            int64_t na_c = below ? c : -1;
+            double nb_x = above ? x : __builtin_inf();
+            int64_t nb_c = above ? c : INT64_MAX;
+            for (int o = 16; o > 0; o >>= 1) {
+                const double ox = __shfl_xor(na_x, o);
+                const int64_t oc = __shfl_xor(na_c, o);
+                if (ox > na_x) { na_x = ox; na_c = oc; }
+                const double px = __shfl_xor(nb_x, o);
+                const int64_t pc = __shfl_xor(nb_c, o);
+                if (px < nb_x) { nb_x = px; nb_c = pc; }
+            }
+            if (na_c >= 0) { a = na_x; ca = na_c; }
+            if (nb_c != INT64_MAX) bb = nb_x;
+        }
+        for (int u = 0; u < 2; ++u) {
+            ta[u] = __shfl(a, 32 * u);
+            tb[u] = __shfl(bb, 32 * u);
+            na[u] = __shfl(ca, 32 * u);
+        }
+        quota[0] = pr->il - 1 - na[0];   // of the il bracket's eigenvalues, these lie below il
+        quota[1] = pr->iu - na[1];       // of the iu bracket's eigenvalues, these lie up to iu
+    }
     for (int b = 0; b < nb && !err; ++b) {
         const int64_t nbk = B[b].n;
         int64_t w0, w1;
@@ -3135,6 +3196,16 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
             const int c = negcount_T(S, P.d + B[b].row0, P.e + B[b].row0, nbk, tsc, sig);
             w0 = (int64_t)__shfl(c, 0) + 1;
             w1 = (int64_t)__shfl(c, 1);
+        } else if (split_index) {
+            const double sig = (l == 0) ? ta[0] : (l == 1) ? tb[0] : (l == 2) ? ta[1] : tb[1];
+            const int c = negcount_T(S, P.d + B[b].row0, P.e + B[b].row0, nbk, tsc, sig);
+            const int64_t c0 = __shfl(c, 0), c1 = __shfl(c, 1), c2 = __shfl(c, 2), c3 = __shfl(c, 3);
+            const int64_t x = max((int64_t)0, min(c1 - c0, quota[0]));
+            const int64_t y = max((int64_t)0, min(c3 - c2, quota[1]));
+            quota[0] -= x;
+            quota[1] -= y;
+            w0 = min(c0 + x + 1, nbk + 1);
+            w1 = min(c2 + y, nbk);
         } else {
             w0 = pr->il;
             w1 = pr->iu;
@@ -3148,6 +3219,7 @@ extern "C" __global__ __launch_bounds__(64) void mrrr_setup_kernel(Params P) {
         }
         if (w1 >= w0) m += w1 - w0 + 1;
     }
+    if (split_index && !err && m != pr->iu - pr->il + 1) err = kErrInternal;
     __threadfence_block();
     __syncthreads();
     if (l == 0) {
@@ -3268,45 +3340,36 @@ extern "C" __global__ __launch_bounds__(256) void mrrr_cycle_kernel(Params P, in
 }
 
 // Position i of a marked problem receives column col[i].  The permutation is
-// applied in place cycle by cycle: the wave that holds a cycle's smallest
-// index (its leader, from mrrr_cycle_kernel) moves it, 512 rows at a time
-// through registers.
+// applied in place cycle by cycle: for the cycle whose smallest index (its
+// leader, from mrrr_cycle_kernel) is p, the rows of each 64-row chunk move
+// along the cycle independently of the other chunks, so a wave takes one
+// (leader, chunk) item at a time and a long cycle is spread over as many
+// waves as it has chunks (columns of split blocks with equal spectra
+// interleave into cycles of thousands).
 extern "C" __global__ __launch_bounds__(64) void mrrr_permute_kernel(Params P, int rounds) {   // rounds: index of the last round
-    constexpr int kR = 8;
     const int l = lane_id();
     const Problem pr = P.probs[blockIdx.y];
     if (!(pr.flags & 2) || !P.jobz) return;
     const int64_t m = pr.m, n = pr.n, ldz = pr.ldz;
+    const int64_t nch = (n + kWave - 1) / kWave;
     const int32_t* col = P.perm + 2 * pr.row0;
     const int32_t* lead = cycle_buf(P, pr, (rounds & 1) ? 1 : 0);   // written by round `rounds`
     double* Z = P.Z + pr.zoff;
-    for (int64_t p = blockIdx.x; p < m; p += gridDim.x) {
+    for (int64_t it = blockIdx.x; it < m * nch; it += gridDim.x) {
+        const int64_t p = it / nch;
         if (col[p] == p || lead[p] != p) continue;
-        for (int64_t r0 = 0; r0 < n; r0 += kWave * kR) {
-            double keep[kR];
-#pragma unroll
-            for (int u = 0; u < kR; ++u) {
-                const int64_t r = r0 + u * kWave + l;
-                keep[u] = (r < n) ? Z[p * ldz + r] : 0.0;
+        const int64_t r = (it - p * nch) * kWave + l;
+        const bool in = r < n;
+        const double keep = in ? Z[p * ldz + r] : 0.0;
+        int64_t pp = p;
+        for (int64_t guard = 0; guard <= m; ++guard) {
+            const int64_t sidx = col[pp];
+            if (sidx == p) {
+                if (in) Z[pp * ldz + r] = keep;
+                break;
             }
-            int64_t pp = p;
-            for (int64_t guard = 0; guard <= m; ++guard) {
-                const int64_t sidx = col[pp];
-                if (sidx == p) {
-#pragma unroll
-                    for (int u = 0; u < kR; ++u) {
-                        const int64_t r = r0 + u * kWave + l;
-                        if (r < n) Z[pp * ldz + r] = keep[u];
-                    }
-                    break;
-                }
-#pragma unroll
-                for (int u = 0; u < kR; ++u) {
-                    const int64_t r = r0 + u * kWave + l;
-                    if (r < n) Z[pp * ldz + r] = Z[sidx * ldz + r];
-                }
-                pp = sidx;
-            }
+            if (in) Z[pp * ldz + r] = Z[sidx * ldz + r];
+            pp = sidx;
         }
     }
 }
@@ -3374,6 +3437,23 @@ extern "C" __global__ void mrrr_quot_kernel(const double* a, const double* b, do
     if (i < n) q[i] = quot(recip(b[i]), a[i]);
 }
 
+// Single/double form (Sec. 5.1.1): the caller's FP32 data in, FP64 inside,
+// FP32 results out.  Widening is exact; narrowing rounds to nearest.
+extern "C" __global__ void mrrr_widen_kernel(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (double)x[i];
+}
+
+// dst(i, j) = src(i, j) for i < rows, j < cols; one 256-thread block covers
+// 256 consecutive rows of one column (blockIdx.y), so reads and writes are
+// contiguous along the column.
+extern "C" __global__ void mrrr_narrow_kernel(const double* __restrict__ src, int64_t lds, float* __restrict__ dst,
+                                              int64_t ldd, int64_t rows, int64_t cols) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y)
+        if (i < rows) dst[j * ldd + i] = (float)src[j * lds + i];
+}
+
 // ------------------------------------------------------------ launchers
 
 namespace mrrr {
@@ -3381,6 +3461,22 @@ namespace mrrr {
 hipError_t launch_quot(const double* a, const double* b, double* q, int64_t n, hipStream_t s) {
     const int64_t grid = (n + 255) / 256;
     if (grid > 0) hipLaunchKernelGGL(mrrr_quot_kernel, dim3((unsigned)grid), dim3(256), 0, s, a, b, q, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(const float* x, double* y, int64_t n, hipStream_t s) {
+    const int64_t grid = (n + 255) / 256;
+    if (grid > 0) hipLaunchKernelGGL(mrrr_widen_kernel, dim3((unsigned)grid), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_narrow(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t rows, int64_t cols,
+                         hipStream_t s) {
+    const int64_t gx = (rows + 255) / 256;
+    const int64_t gy = cols < 65535 ? cols : 65535;
+    if (gx > 0 && gy > 0)
+        hipLaunchKernelGGL(mrrr_narrow_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, src, lds, dst, ldd,
+                           rows, cols);
     return hipGetLastError();
 }
 
@@ -3411,7 +3507,7 @@ hipError_t launch_finalize(const Params& P, hipStream_t s) {
     while ((int64_t)1 << (rounds - 1) < std::max<int64_t>(P.total_rows, 2)) ++rounds;
     const unsigned gc = (unsigned)std::max(1, std::min(256, 65536 / std::max(1, (int)P.nprob)));
     for (int r = 0; r < rounds; ++r) hipLaunchKernelGGL(mrrr_cycle_kernel, dim3(gc, P.nprob), dim3(256), 0, s, P, r);
-    const unsigned gx = (unsigned)std::max(1, std::min(512, 65536 / std::max(1, (int)P.nprob)));
+    const unsigned gx = (unsigned)std::max(1, std::min(8192, 262144 / std::max(1, (int)P.nprob)));
     hipLaunchKernelGGL(mrrr_permute_kernel, dim3(gx, P.nprob), dim3(kWave), 0, s, P, rounds - 1);
     return hipGetLastError();
 }

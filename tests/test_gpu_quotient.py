@@ -140,8 +140,17 @@ def test_edge_of_overflow():
     overflows."""
     rng = np.random.default_rng(3)
     n = 4096
-    a = np.ldexp(rng.uniform(1.0, 2.0, n), 1023)
-    b = rng.uniform(0.999999, 1.000001, n)
+    # a near the top binade, b around 1: about a quarter of the quotients
+    # overflow; then the largest double over divisors a few ulps either side
+    # of 1, whose exact quotients straddle the overflow threshold
+    a = np.ldexp(rng.uniform(1.9, 2.0, n), 1023)
+    b = rng.uniform(0.95, 1.05, n)
+    big = np.finfo(np.float64).max
+    j = np.arange(1, 65, dtype=np.float64)
+    a = np.concatenate([a, np.full(128, big), np.full(128, -big)])
+    edge = np.concatenate([1.0 - j * 2.0 ** -53, 1.0 + j * 2.0 ** -52])
+    b = np.concatenate([b, edge, edge])
+    n = len(a)
     with np.errstate(over="ignore"):
         ieee = a / b
     q = _quot(a, b)

@@ -127,13 +127,67 @@ def test_splitting(orc):
     check_pairs(d, e, w, Z, wo, Zo, tnorm=M.tnorm_of(orc.solve(d, e, vectors=False)))
 
 
-def test_index_range_with_split_is_refused():
-    from paper_1401_4950_amd import MrrrError
-    d, e = ti.random_uniform(100, 1)
-    e[40] = 0.0
-    with pytest.raises(MrrrError) as ex:
-        gpu_solve(d, e, select="i", select_range=(3, 10))
-    assert ex.value.code == 5
+@pytest.mark.parametrize("il,iu", [(1, 1), (3, 10), (40, 140), (95, 160), (1, 300), (300, 300), (151, 150)])
+def test_index_range_over_split_blocks(orc, il, iu):
+    """An index range over a matrix that splits (Sec. 3.2.1): ranks in the
+    direct sum of the blocks, against the oracle, which solves every block
+    and merges by value.  Three blocks whose spectra interleave and a 1x1
+    block, so that every range cuts several blocks."""
+    d1, e1 = ti.random_uniform(120, 11)
+    d2, e2 = ti.random_uniform(120, 12)
+    d3, e3 = ti.random_uniform(59, 13)
+    d = np.concatenate([d1, d2, [0.123], d3])
+    e = np.concatenate([e1, [0.0], e2, [0.0], [0.0], e3])
+    assert len(d) == 300 and len(e) == 299
+    w_all, Z_all = orc.solve(d, e)
+    tn = M.tnorm_of(w_all)
+    if iu < il:
+        w = gpu_solve(d, e, select="i", select_range=(il, iu), eigvals_only=True)
+        assert len(w) == 0
+        return
+    w, Z = gpu_solve(d, e, select="i", select_range=(il, iu))
+    wo = orc.solve(d, e, "index", il=il, iu=iu, vectors=False)
+    check_pairs(d, e, w, Z, wo, tnorm=tn, full=(w_all, Z_all, il - 1))
+
+
+def test_index_range_over_identical_blocks(orc):
+    """Identical blocks: every eigenvalue occurs once per block, exactly; a
+    range that cuts through such a tie takes the copies of the lower blocks
+    first, so the eigenvalues match the oracle's stable merge and each column
+    lives on one block, with no two columns on the same block and value."""
+    d1, e1 = ti.random_uniform(40, 5)
+    nb = 4
+    d = np.tile(d1, nb)
+    e = np.concatenate([np.concatenate([e1, [0.0]]) for _ in range(nb)])[:-1]
+    w_all = orc.solve(d, e, vectors=False)
+    tn = M.tnorm_of(w_all)
+    for il, iu in [(2, 3), (6, 9), (37, 122), (158, 160)]:
+        w, Z = gpu_solve(d, e, select="i", select_range=(il, iu))
+        wo = orc.solve(d, e, "index", il=il, iu=iu, vectors=False)
+        assert np.max(np.abs(w - wo)) <= 4 * len(d) * M.EPS * tn
+        r, o = M.scaled(d, e, w, Z, tn)
+        assert r <= 10 and o <= 100, (r, o)
+        owner = np.argmax(np.abs(Z).reshape(nb, 40, -1).max(axis=1), axis=0)
+        support = (np.abs(Z).reshape(nb, 40, -1).max(axis=1) > 0).sum(axis=0)
+        assert np.all(support == 1)
+        # ties in block order: among equal eigenvalues the lower blocks come first
+        for i in range(len(w) - 1):
+            if w[i] == w[i + 1]:
+                assert owner[i] < owner[i + 1], (il, iu, i)
+
+
+def test_index_range_over_glued_wilkinson_split_by_zero_glue(orc):
+    """W21+ blocks with a zero glue: 21-fold ties of every eigenvalue value
+    across blocks, and the pairs inside each block that agree to 1e-14."""
+    d, e = ti.glued_wilkinson(21 * 12, glue=0.0)
+    w_all = orc.solve(d, e, vectors=False)
+    tn = M.tnorm_of(w_all)
+    for il, iu in [(1, 5), (100, 130), (230, 252)]:
+        w, Z = gpu_solve(d, e, select="i", select_range=(il, iu))
+        wo = orc.solve(d, e, "index", il=il, iu=iu, vectors=False)
+        assert np.max(np.abs(w - wo)) <= 4 * len(d) * M.EPS * tn, (il, iu)
+        r, o = M.scaled(d, e, w, Z, tn)
+        assert r <= 10 and o <= 100, (il, iu, r, o)
 
 
 def test_values_only_matches_vectors_run(orc):
