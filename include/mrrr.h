@@ -40,7 +40,9 @@ typedef enum {
     MRRR_OK = 0,
     /* A new representation was accepted although its element growth was
      * above the threshold (Alg. 3.8 keeps the candidate of least growth when
-     * none passes), or a cluster hit the depth limit.  Outputs are filled;
+     * none passes) and the check of conditional element growth after the tree
+     * did not clear it (see stats->n_cond_checked), or a cluster hit the depth
+     * limit.  Outputs are filled;
      * stats->n_unverified_rrr says how often, and the columns of such
      * clusters are checked for orthogonality (and corrected when needed)
      * after the tree, with stats->n_check_failed counting the ones that could
@@ -92,6 +94,11 @@ typedef struct {
                                 max |Z^T Z - I| over them exceeds
                                 check_tol * n * eps (20); 0 corrects every
                                 checked cluster */
+    double cond_growth_k;    /* k_elg of the check of conditional element
+                                growth after the tree (Sec. 3.1.2), 10; the
+                                bound is (k_elg / 3) n spdiam; 0 switches the
+                                check off (every representation that failed the
+                                element-growth bound then stays unverified) */
 } mrrr_options_t;
 
 /* One record per executed device task (the per-task timeline of the
@@ -119,7 +126,11 @@ typedef struct {
     int64_t largest_cluster;   /* biggest cluster at any depth */
     int32_t dmax;              /* depth of the representation tree */
     int32_t pad;
-    int64_t n_unverified_rrr;  /* RRRs accepted without passing the test */
+    int64_t n_unverified_rrr;  /* RRRs accepted without passing the element-
+                                  growth bound of Alg. 3.8 (see n_cond_checked:
+                                  those shown afterwards to exhibit conditional
+                                  element growth no longer set
+                                  MRRR_WARN_UNVERIFIED) */
     int64_t n_bisect_fallback; /* singletons that fell back to bisection */
     int64_t n_nan_retry;       /* twisted-factorisation and eigenvector passes that one
                                   worker redid in IEEE form after a NaN */
@@ -148,6 +159,19 @@ typedef struct {
                                   columns: not checked as a whole; those of
                                   their descendants that are unverified and
                                   hold at most 64 wanted columns are */
+    int64_t n_cond_checked;    /* representations counted in n_unverified_rrr
+                                  that were checked after the tree for
+                                  conditional element growth (Sec. 3.1.2):
+                                  || |L||D||L^T| |z| || <= (k/3) n spdiam ||z||,
+                                  k = opts->cond_growth_k
+                                  for the computed vector z of every wanted
+                                  member (of 512 evenly spread ones, both ends
+                                  included, in a cluster of more; needs
+                                  jobz = 1) */
+    int64_t n_cond_failed;     /* of those, representations with a vector above
+                                  the bound */
+    double max_cond_growth;    /* largest || |L||D||L^T| |z| || / (||z|| spdiam)
+                                  found by that check */
 } mrrr_stats_t;
 
 /* Creates a handle on HIP device `device`.  The handle owns a workspace that

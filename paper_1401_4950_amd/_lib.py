@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
         ("timeout_s", ctypes.c_double), ("arena_scale", ctypes.c_double),
         ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int64),
         ("lanes_per_eig", ctypes.c_int32), ("bundle", ctypes.c_int32),
-        ("tune", ctypes.c_void_p), ("check_tol", ctypes.c_double),
+        ("tune", ctypes.c_void_p), ("check_tol", ctypes.c_double), ("cond_growth_k", ctypes.c_double),
     ]
 
 
@@ -56,7 +56,8 @@ class Stats(ctypes.Structure):
         ("arena_bytes", ctypes.c_int64), ("ms", ctypes.c_double), ("tree_ms", ctypes.c_double),
         ("n_sturm_guarded", ctypes.c_int64), ("n_checked", ctypes.c_int64),
         ("n_reorthogonalized", ctypes.c_int64), ("n_check_failed", ctypes.c_int64),
-        ("n_check_wide", ctypes.c_int64),
+        ("n_check_wide", ctypes.c_int64), ("n_cond_checked", ctypes.c_int64),
+        ("n_cond_failed", ctypes.c_int64), ("max_cond_growth", ctypes.c_double),
     ]
 
     def as_dict(self):

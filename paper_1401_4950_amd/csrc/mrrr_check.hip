@@ -386,6 +386,142 @@ extern "C" __global__ __launch_bounds__(kRepThreads) void mrrr_repair_kernel(Par
 
 namespace mrrr {
 
+// ------------------------------------------------ conditional element growth
+//
+// A representation M = L D L^T whose element growth max |D| failed the test
+// of Alg. 3.8 may still exhibit conditional element growth for its members
+// (Sec. 3.1.2): for every relative perturbation M~ of its data bounded by xi,
+// ||(M~ - M) z_i|| <= k_elg n xi spdiam for the computed eigenvectors z_i.  To
+// first order the entries of M~ - M are bounded by 3 xi times those of
+// |L||D||L^T| (tridiagonal: |d_{j-1} l_{j-1}|, |d_j| + |d_{j-1}| l_{j-1}^2,
+// |d_j l_j|), so the test taken here is
+//     || |L||D||L^T| |z| || <= (k_elg / 3) n spdiam ||z||,   k_elg = 10 (option),
+// for the wanted members' final vectors (computed from this representation or
+// from a descendant), over all rows of the block: every member of a cluster of
+// up to kGrowthSample wanted members, else kGrowthSample members spread evenly
+// over the cluster with both ends included (a chain of nested clusters of
+// thousands would otherwise cost a pass over Z per level).  (The first condition
+// of the definition, ||M~ - M|| <= spdiam, holds for xi = O(n eps) unless the
+// growth exceeds 1e11 spdiam, where this test fails as well.)
+
+// Exclusive prefix sum of the records' column counts (one workgroup).
+extern "C" __global__ __launch_bounds__(1024) void mrrr_growth_prefix_kernel(Params P) {
+    __shared__ int64_t part[1024];
+    if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int64_t top = P.ctl->grw_top;
+    const int64_t nrec = top < P.grw_cap ? top : P.grw_cap;
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int64_t chunk = (nrec + nt - 1) / nt;
+    const int64_t a = (int64_t)t * chunk, b = (a + chunk < nrec) ? a + chunk : nrec;
+    int64_t sum = 0;
+    for (int64_t r = a; r < b; ++r) sum += P.grw[r].mc;
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int k = 0; k < nt; ++k) {
+            const int64_t v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+        P.ctl->grw_cols = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int64_t r = a; r < b; ++r) {
+        P.grw[r].col0 = acc;
+        acc += P.grw[r].mc;
+    }
+}
+
+// One wavefront per column of a record: sum over the block's rows of
+// w_j^2, w = |L||D||L^T| |z|, and of z_j^2.  Each step covers 4 x 64 rows
+// with all twelve loads of a lane in flight at once; the neighbours z_{j-1},
+// z_{j+1}, d_{j-1}, l_{j-1} come by shuffles within a 64-row group, from the
+// adjacent group's edge lane, or (at the step's two ends) by the edge lanes'
+// own loads.
+extern "C" __global__ __launch_bounds__(256) void mrrr_growth_kernel(Params P) {
+    constexpr int U = 4;
+    if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    const int64_t top = P.ctl->grw_top;
+    const int64_t nrec = top < P.grw_cap ? top : P.grw_cap;
+    const int64_t ncol = P.ctl->grw_cols;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t g = (int64_t)blockIdx.x * 4 + wv; g < ncol; g += (int64_t)gridDim.x * 4) {
+        int64_t lo = 0, hi = nrec - 1;                 // the record holding column g
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (P.grw[mid].col0 <= g) lo = mid; else hi = mid - 1;
+        }
+        GrowthRec* rec = P.grw + lo;
+        const int64_t n = rec->n;
+        const double* D = P.arena + rec->rep;
+        const double* L = D + n;
+        const int64_t k = g - rec->col0;                // k-th checked column of mc
+        const int64_t c = (rec->mc == rec->m) ? k : (k * (rec->m - 1)) / (rec->mc - 1);
+        const double* z = P.Z + rec->z + c * rec->ldz;
+        double ss = 0.0, zz = 0.0;
+        for (int64_t base = 0; base < n; base += (int64_t)U * 64) {
+            double zv[U], dv[U], lv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = base + 64 * u + lane;
+                zv[u] = (j < n) ? z[j] : 0.0;
+                dv[u] = (j < n) ? D[j] : 0.0;
+                lv[u] = (j < n - 1) ? L[j] : 0.0;
+            }
+            // the rows just outside the step, by its edge lanes
+            const int64_t jb = base - 1, je = base + (int64_t)U * 64;
+            double zb = 0.0, db = 0.0, lb = 0.0, ze = 0.0;
+            if (lane == 0 && jb >= 0) { zb = z[jb]; db = D[jb]; lb = L[jb]; }
+            if (lane == 63 && je < n) ze = z[je];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = base + 64 * u + lane;
+                double zp = __shfl_up(zv[u], 1), dp = __shfl_up(dv[u], 1), lp = __shfl_up(lv[u], 1);
+                double zn = __shfl_down(zv[u], 1);
+                // group edges: the neighbouring group's edge lane, or the step's ends
+                const double zpe = (u > 0) ? __shfl(zv[u > 0 ? u - 1 : 0], 63) : zb;
+                const double dpe = (u > 0) ? __shfl(dv[u > 0 ? u - 1 : 0], 63) : db;
+                const double lpe = (u > 0) ? __shfl(lv[u > 0 ? u - 1 : 0], 63) : lb;
+                const double zne = (u + 1 < U) ? __shfl(zv[u + 1 < U ? u + 1 : u], 0) : ze;
+                if (lane == 0) { zp = zpe; dp = dpe; lp = lpe; }
+                if (lane == 63) zn = zne;
+                if (j < n) {
+                    const double w = fabs(dp * lp) * fabs(zp) + (fabs(dv[u]) + fabs(dp * lp * lp)) * fabs(zv[u]) +
+                                     fabs(dv[u] * lv[u]) * fabs(zn);
+                    ss += w * w;
+                    zz += zv[u] * zv[u];
+                }
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            ss += __shfl_xor(ss, o);
+            zz += __shfl_xor(zz, o);
+        }
+        if (lane == 0) {
+            const double G = sqrt(ss / zz);
+            if (!(G <= rec->bound)) {
+                int32_t expect = 0;
+                if (__hip_atomic_compare_exchange_strong(&rec->flag, &expect, (int32_t)1, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                    stat_add(&P.ctl->n_grw_failed, 1);
+            }
+            const double ratio = G / rec->spdiam;
+            const uint64_t bits = (ratio <= 1e300) ? (uint64_t)__double_as_longlong(ratio)
+                                                   : (uint64_t)__double_as_longlong(__builtin_inf());
+            __hip_atomic_fetch_max(&P.ctl->grw_max, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+hipError_t launch_growth(const Params& P, hipStream_t s) {
+    if (!P.jobz || P.grw_cap <= 0 || !(P.cond_k > 0.0)) return hipSuccess;
+    hipLaunchKernelGGL(mrrr_growth_prefix_kernel, dim3(1), dim3(1024), 0, s, P);
+    hipLaunchKernelGGL(mrrr_growth_kernel, dim3(8192), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+
 hipError_t launch_check(const Params& P, hipStream_t s) {
     if (!P.jobz || P.chk_cap <= 0) return hipSuccess;
     const int64_t g = P.chk_cap < 4096 ? P.chk_cap : 4096;

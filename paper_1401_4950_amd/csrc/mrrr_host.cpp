@@ -24,6 +24,7 @@ hipError_t launch_tree(const Params& P, hipStream_t s);
 hipError_t launch_finalize(const Params& P, hipStream_t s);
 hipError_t launch_sign(const Params& P, int64_t ncols_total, hipStream_t s);
 hipError_t launch_check(const Params& P, hipStream_t s);
+hipError_t launch_growth(const Params& P, hipStream_t s);
 hipError_t tree_occupancy(int* blocks_per_cu);
 hipError_t launch_quot(const double* a, const double* b, double* q, int64_t n, hipStream_t s);
 hipError_t launch_widen(const float* x, double* y, int64_t n, hipStream_t s);
@@ -65,12 +66,13 @@ struct DevBuf {
 };
 
 struct Workspace {
-    DevBuf probs, blocks, nodes, q[kNumQ], seq[kNumQ], lo, hi, gap, lo0, hi0, vflag, need, slist, arena, ck, colbuf, perm, ctl, chk;
+    DevBuf probs, blocks, nodes, q[kNumQ], seq[kNumQ], lo, hi, gap, lo0, hi0, vflag, need, slist, arena, ck, colbuf, perm, ctl, chk,
+        grw;
     void release() {
         probs.release(); blocks.release(); nodes.release();
         for (int i = 0; i < kNumQ; ++i) { q[i].release(); seq[i].release(); }
         lo.release(); hi.release(); gap.release(); lo0.release(); hi0.release(); vflag.release(); need.release(); slist.release();
-        arena.release(); ck.release(); colbuf.release(); perm.release(); ctl.release(); chk.release();
+        arena.release(); ck.release(); colbuf.release(); perm.release(); ctl.release(); chk.release(); grw.release();
     }
 };
 
@@ -141,6 +143,7 @@ extern "C" void mrrr_default_options(mrrr_options_t* o) {
     o->timeout_s = 30.0;
     o->arena_scale = 1.0;
     o->check_tol = 20.0;
+    o->cond_growth_k = 10.0;
 }
 
 extern "C" const char* mrrr_status_string(int s) {
@@ -256,6 +259,9 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     // checked clusters are disjoint and hold two columns or more
     const int64_t nchk = std::max<int64_t>(sz.rows / 2, 1);
     ENS(ws.chk, sizeof(CheckRec) * (size_t)nchk);
+    // cluster representations form a laminar family of member sets of two or
+    // more: fewer than rows of them
+    ENS(ws.grw, sizeof(GrowthRec) * r);
 #undef ENS
     P.probs = ws.probs.as<Problem>();
     P.blocks = ws.blocks.as<Block>();
@@ -283,6 +289,8 @@ hipError_t prepare(Workspace& ws, const Sizes& sz, Params& P) {
     P.ctl = ws.ctl.as<Ctl>();
     P.chk = ws.chk.as<CheckRec>();
     P.chk_cap = nchk;
+    P.grw = ws.grw.as<GrowthRec>();
+    P.grw_cap = (int64_t)r;
     P.total_rows = sz.rows;
     return hipSuccess;
 }
@@ -304,6 +312,7 @@ void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int worker
     P.trace_cap = P.trace ? o.trace_cap : 0;
     P.check_tol = o.check_tol;
     P.io_eps = io_eps;
+    P.cond_k = o.cond_growth_k;
 }
 
 int check_options(const mrrr_options_t& o) {
@@ -316,6 +325,7 @@ int check_options(const mrrr_options_t& o) {
     if (o.lanes_per_eig < 1 || o.lanes_per_eig > kWave || (o.lanes_per_eig & (o.lanes_per_eig - 1))) return 1;
     if (o.bundle < 1 || o.bundle > kWave) return 1;
     if (!(o.check_tol >= 0.0 && o.check_tol <= 1e15)) return 1;
+    if (!(o.cond_growth_k >= 0.0 && o.cond_growth_k <= 1e300)) return 1;
     return 0;
 }
 
@@ -367,6 +377,14 @@ int read_back(mrrr_handle_t h, const Params& P, Ctl* ctl_h, std::vector<Problem>
     return MRRR_OK;
 }
 
+// Representations accepted without passing a growth test: those that failed
+// the element-growth bound of Alg. 3.8 and were not shown afterwards to
+// exhibit conditional element growth for their members' vectors.
+int64_t still_unverified(const Ctl& c) {
+    const int64_t passed = c.grw_top - c.n_grw_failed;
+    return c.n_unverified - (passed > 0 ? passed : 0);
+}
+
 void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms, float tree_ms = 0.f) {
     if (!st) return;
     std::memset(st, 0, sizeof(*st));
@@ -383,6 +401,13 @@ void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms, float tree_
     st->n_reorthogonalized = c.n_repaired;
     st->n_check_failed = c.n_check_failed;
     st->n_check_wide = c.n_check_wide;
+    st->n_cond_checked = c.grw_top;
+    st->n_cond_failed = c.n_grw_failed;
+    {
+        double g;
+        std::memcpy(&g, &c.grw_max, sizeof(g));
+        st->max_cond_growth = g;
+    }
     st->qd_steps = c.qd_steps;
     st->n_tasks = c.n_tasks;
     st->n_singleton_tasks = c.n_single;
@@ -401,6 +426,7 @@ hipError_t enqueue_solve(const Params& P, int64_t ncols_total, bool sign, hipStr
     if (ev_tree && (e = hipEventRecord(ev_tree[0], s)) != hipSuccess) return e;
     if ((e = launch_tree(P, s)) != hipSuccess) return e;
     if (ev_tree && (e = hipEventRecord(ev_tree[1], s)) != hipSuccess) return e;
+    if ((e = launch_growth(P, s)) != hipSuccess) return e;
     if ((e = launch_check(P, s)) != hipSuccess) return e;
     if ((e = launch_finalize(P, s)) != hipSuccess) return e;
     if (sign && P.jobz && (e = launch_sign(P, ncols_total, s)) != hipSuccess) return e;
@@ -496,7 +522,7 @@ int solve_single(mrrr_handle_t h, int64_t n, const double* d, const double* e, i
         }
         *m = ph[0].m;
         fill_stats(stats, c, ph[0].m, ms, tms);
-        if (status == MRRR_OK && c.n_unverified > 0) status = MRRR_WARN_UNVERIFIED;
+        if (status == MRRR_OK && still_unverified(c) > 0) status = MRRR_WARN_UNVERIFIED;
         break;
     }
     return status;
@@ -773,7 +799,7 @@ extern "C" int mrrr_dstemr_batched(mrrr_handle_t h, int64_t batch, const int64_t
             continue;
         }
         fill_stats(stats, c, rows, ms);
-        if (st == MRRR_OK && c.n_unverified > 0) st = MRRR_WARN_UNVERIFIED;
+        if (st == MRRR_OK && still_unverified(c) > 0) st = MRRR_WARN_UNVERIFIED;
         return st;
     }
     return MRRR_ENOMEM;

@@ -106,6 +106,25 @@ struct CheckRec {
     int64_t pad[2];
 };
 
+// Representations that passed no element-growth test, checked after the tree
+// for conditional element growth (Sec. 3.1.2, Definition of conditional
+// element growth; the test of remark (3) on Alg. 3.8) against the computed
+// eigenvectors of their wanted members.
+constexpr int64_t kGrowthSample = 512;   // most member columns checked per representation
+struct GrowthRec {
+    int64_t rep;      // arena offset of D+ (L+ follows at rep + n)
+    int64_t z;        // offset in Z of the first wanted member's column, at the block's first row
+    int64_t ldz;
+    int64_t n;        // rows of the block
+    int64_t m;        // wanted member columns
+    int64_t mc;       // columns checked: all m, or kGrowthSample spread evenly (both ends included)
+    int64_t col0;     // device: first column of this record in the flattened list (prefix sum)
+    double bound;     // the largest acceptable || |L+||D+||L+^T| |z| || / ||z||
+    double spdiam;    // spectral diameter of the block's root (the same frame)
+    int32_t flag;     // device: 1 once a column exceeded the bound
+    int32_t pad;
+};
+
 // Words that many workers hit (queue heads and tails, the pending count, the
 // error flag) each sit on a 256-byte line of their own, so that polling one
 // does not contend with updates of another.
@@ -132,6 +151,10 @@ struct Ctl {
     int64_t chk_top;      // records in Params::chk
     int64_t n_checked, n_repaired, n_check_failed;
     int64_t n_check_wide; // unverified clusters too wide to be checked themselves
+    int64_t grw_top;      // records in Params::grw
+    int64_t n_grw_failed; // of those, representations with a column above the bound
+    uint64_t grw_max;     // largest ratio || |L||D||L^T| |z| || / (||z|| spdiam) seen (bits of a double)
+    int64_t grw_cols;     // columns in all records (after the prefix sum)
 #ifdef __HIPCC__
     __device__ __host__ uint64_t* head(int q) { return head_ + q * kLineU64; }
     __device__ __host__ uint64_t* tail(int q) { return tail_ + q * kLineU64; }
@@ -188,6 +211,9 @@ struct Params {
     double check_tol;     // correct when max |Z^T Z - I| > check_tol n eps
     double io_eps;        // unit roundoff of the caller's data format when it is
                           // coarser than FP64 (single/double: 2^-24), else 0
+    GrowthRec* grw;       // representations checked for conditional element growth
+    int64_t grw_cap;
+    double cond_k;        // k_elg of that check; 0: no check
 };
 
 }  // namespace mrrr

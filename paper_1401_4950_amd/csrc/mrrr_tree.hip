@@ -2716,6 +2716,32 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
                 add_stat(&P.ctl->n_check_wide, 1);
             }
         }
+        // every unverified representation with wanted members: checked after
+        // the tree for conditional element growth against their vectors
+        if (unverified && P.jobz && P.cond_k > 0.0) {
+            const int c0 = max(p, blk.w0), c1 = min(q, blk.w1);
+            const int64_t m = (int64_t)c1 - c0 + 1;
+            if (m >= 1) {
+                const int64_t k = __hip_atomic_fetch_add(&P.ctl->grw_top, (int64_t)1, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                if (k < P.grw_cap) {
+                    const Problem pr = P.probs[blk.prob];
+                    GrowthRec g;
+                    g.rep = off;
+                    g.z = pr.zoff + (blk.col0 + (c0 - blk.w0)) * pr.ldz + (blk.row0 - pr.row0);
+                    g.ldz = pr.ldz;
+                    g.n = n;
+                    g.m = m;
+                    g.mc = m < kGrowthSample ? m : kGrowthSample;
+                    g.col0 = 0;
+                    g.bound = (P.cond_k / 3.0) * (double)n * spd;   // see mrrr_growth_kernel
+                    g.spdiam = spd;
+                    g.flag = 0;
+                    g.pad = 0;
+                    P.grw[k] = g;
+                }
+            }
+        }
         Node nd;
         nd.data = off;
         nd.block = par.block;

@@ -472,3 +472,65 @@ def test_tiny_diagonal_entries_use_the_guarded_count(orc):
     assert mr.last_stats()["n_sturm_guarded"] > 0
     wo, Zo = orc.solve(d, e)
     check_pairs(d, e, w, Z, wo, Zo)
+
+
+# ------------------------------------------------ conditional element growth
+
+
+@pytest.mark.parametrize("fam,n", [("121", 3000), ("clement", 3000), ("glued_wilkinson", 4200), ("random", 3000)])
+def test_conditional_growth_clears_representations(orc, fam, n):
+    """Representations that fail the element-growth bound of Alg. 3.8 are
+    checked after the tree for conditional element growth (Sec. 3.1.2)
+    against their members' computed vectors; the bound (10/3) n spdiam
+    clears them on these families, so the solve returns MRRR_OK, while
+    parity is unchanged.  The largest ratio found is far below the bound."""
+    import paper_1401_4950_amd as mr
+    d, e = ti.family(fam, n, 0)
+    w, Z = gpu_solve(d, e)
+    st = mr.last_stats()
+    if st["n_unverified_rrr"] > 0:
+        assert st["n_cond_checked"] == st["n_unverified_rrr"]
+        assert st["n_cond_failed"] == 0
+        assert 0.0 < st["max_cond_growth"] <= (10.0 / 3.0) * n
+    wo, Zo = orc.solve(d, e)
+    check_pairs(d, e, w, Z, wo, Zo)
+
+
+def test_conditional_growth_bound_enforced():
+    """With k_elg tiny every checked representation fails: all are counted,
+    the status is MRRR_WARN_UNVERIFIED (the binding returns it without
+    raising), and the outputs are those of the default run bit for bit (the
+    check only reads Z).  With the check off nothing is checked."""
+    import paper_1401_4950_amd as mr
+    d, e = ti.family("random", 2000, 0)
+    w0, Z0 = gpu_solve(d, e)
+    st0 = mr.last_stats()
+    assert st0["n_unverified_rrr"] > 0 and st0["n_cond_checked"] > 0
+    w1, Z1 = gpu_solve(d, e, cond_growth_k=1e-30)
+    st1 = mr.last_stats()
+    assert st1["n_cond_checked"] == st0["n_cond_checked"] and st1["n_cond_failed"] == st1["n_cond_checked"]
+    assert np.array_equal(w0, w1) and np.array_equal(Z0, Z1)
+    gpu_solve(d, e, cond_growth_k=0.0)
+    st2 = mr.last_stats()
+    assert st2["n_cond_checked"] == 0 and st2["n_cond_failed"] == 0
+
+
+def test_conditional_growth_status_through_the_c_abi():
+    import ctypes
+    import torch
+    import paper_1401_4950_amd as mr
+    from paper_1401_4950_amd import _lib
+    d, e = ti.family("random", 2000, 0)
+    dt, et = to_dev(d), to_dev(e)
+    w = torch.empty(2000, dtype=torch.float64, device="cuda:0")
+    Z = torch.empty(2000 * 2000, dtype=torch.float64, device="cuda:0")
+    h = mr._handle(torch.device("cuda:0"))
+    m = ctypes.c_int64(0)
+    st = _lib.Stats()
+    for k, want in ((10.0, 0), (1e-30, 1)):
+        o = _lib.default_options(cond_growth_k=k)
+        code = _lib.load().mrrr_dstemr(h, 2000, ctypes.c_void_p(dt.data_ptr()), ctypes.c_void_p(et.data_ptr()), 0,
+                                       0.0, 0.0, 0, 0, ctypes.byref(o), ctypes.byref(m),
+                                       ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(Z.data_ptr()), 2000,
+                                       ctypes.byref(st))
+        assert code == want, (k, code, st.n_unverified_rrr, st.n_cond_checked, st.n_cond_failed)
