@@ -172,6 +172,12 @@ typedef struct {
                                   the bound */
     double max_cond_growth;    /* largest || |L||D||L^T| |z| || / (||z|| spdiam)
                                   found by that check */
+    int64_t n_factor_quotient; /* shift selections (Alg. 3.8) that one worker
+                                  redid in the quotient form of the stationary
+                                  transform: data, shift or pivots outside the
+                                  range of the division-free form, or no
+                                  candidate within the growth bound while one
+                                  overflowed */
 } mrrr_stats_t;
 
 /* Creates a handle on HIP device `device`.  The handle owns a workspace that

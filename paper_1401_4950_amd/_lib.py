@@ -58,6 +58,7 @@ class Stats(ctypes.Structure):
         ("n_reorthogonalized", ctypes.c_int64), ("n_check_failed", ctypes.c_int64),
         ("n_check_wide", ctypes.c_int64), ("n_cond_checked", ctypes.c_int64),
         ("n_cond_failed", ctypes.c_int64), ("max_cond_growth", ctypes.c_double),
+        ("n_factor_quotient", ctypes.c_int64),
     ]
 
     def as_dict(self):

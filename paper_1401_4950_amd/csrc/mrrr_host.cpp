@@ -355,11 +355,11 @@ Sizes base_sizes(int64_t rows, int64_t nprob, int64_t kwork, int64_t nmax, doubl
     sz.qcap[kQRefine] = (uint64_t)std::max<int64_t>(65536, 2 * rows + 1024);
     sz.qcap[kQCluster] = (uint64_t)std::max<int64_t>(16384, rows + 1024);
     sz.qcap[kQSingle] = (uint64_t)std::max<int64_t>(16384, rows + 1024);
-    // node pool: 4 n + 128 doubles per representation (the root: two
-    // candidates of D and L; a cluster: D+ and L+ of the new representation
-    // and the checkpoints of the shift selection); start from a few hundred
-    // nodes of the largest block size
-    const double per_node = 4.0 * (double)nmax + 128.0;
+    // node pool: 4 n + kNodeExtra doubles per representation (D and L of
+    // the new representation, the checkpoints of the factorisation and the
+    // cooperation block); start from a few hundred nodes of the largest block
+    // size
+    const double per_node = 4.0 * (double)nmax + (double)kNodeExtra;
     const double nodes = std::min<double>((double)kwork + 2.0 * nprob, 256.0 + (double)kwork / 4.0);
     double a = per_node * std::max(nodes, 8.0 * nprob) * std::max(arena_scale, 1e-3);
     const double cap = per_node * ((double)kwork + 2.0 * nprob + 8.0) * std::max(1.0, arena_scale);
@@ -397,6 +397,7 @@ void fill_stats(mrrr_stats_t* st, const Ctl& c, int64_t m, float ms, float tree_
     st->n_bisect_fallback = c.n_fallback;
     st->n_nan_retry = c.n_nan;
     st->n_sturm_guarded = c.n_sturm;
+    st->n_factor_quotient = c.n_fac_quot;
     st->n_checked = c.n_checked;
     st->n_reorthogonalized = c.n_repaired;
     st->n_check_failed = c.n_check_failed;
@@ -680,11 +681,11 @@ int build_plan(mrrr_handle_t h, mrrr_batched_plan_s* pl) {
         zpack += nb * nb;
     }
     Sizes sz = base_sizes(rows, batch, rows, nmax, pl->opts.arena_scale);
-    // each block's root and clusters draw 4 n_b + 128 doubles; budget by sum n_b
+    // each block's root and clusters draw 4 n_b + kNodeExtra doubles; budget by sum n_b
     double arena = 0.0;
     for (int64_t b = 0; b < batch; ++b) {
         const double nb = (double)(pl->noff[b + 1] - pl->noff[b]);
-        arena += (4.0 * nb + 128.0) * std::min(nb + 2.0, 64.0 + nb / 4.0);
+        arena += (4.0 * nb + (double)kNodeExtra) * std::min(nb + 2.0, 64.0 + nb / 4.0);
     }
     sz.arena = (uint64_t)std::max(arena * std::max(pl->opts.arena_scale, 1e-3), 1024.0);
     sz.ck = std::max<int64_t>(ck, 1);

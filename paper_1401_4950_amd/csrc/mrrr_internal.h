@@ -20,6 +20,10 @@ constexpr int kTile = 64;      // rows of a representation staged in LDS at once
 constexpr int kCkb = 16;       // rows between checkpoints of the twisted solver
 constexpr int kCkSlots = 6;    // doubles per checkpoint and eigenvalue
 constexpr int kNumQ = 3;       // 0: refine, 1: root + cluster, 2: singleton
+// node pool doubles per representation of an n-row block: 4 n + kNodeExtra
+// (D and L; the shift selection's two checkpoint arrays of n + 64; the block
+// of the cooperative end refinement)
+constexpr int64_t kNodeExtra = 512;
 constexpr int kQRefine = 0, kQCluster = 1, kQSingle = 2;
 
 enum TaskType : int32_t {
@@ -155,6 +159,7 @@ struct Ctl {
     int64_t n_grw_failed; // of those, representations with a column above the bound
     uint64_t grw_max;     // largest ratio || |L||D||L^T| |z| || / (||z|| spdiam) seen (bits of a double)
     int64_t grw_cols;     // columns in all records (after the prefix sum)
+    int64_t n_fac_quot;   // shift selections redone in quotient form
 #ifdef __HIPCC__
     __device__ __host__ uint64_t* head(int q) { return head_ + q * kLineU64; }
     __device__ __host__ uint64_t* tail(int q) { return tail_ + q * kLineU64; }

@@ -180,6 +180,7 @@ struct Shared {
     double info_d[2];
     int32_t redo;                             // twisted / Getvec passes redone in IEEE form
     int32_t redo_sturm;                       // Sturm counts redone in guarded form
+    int32_t redo_fac;                         // shift selections redone in quotient form
     int32_t sl_a[kMaxSlices];                 // refinement slices being pushed: first member,
     int8_t sl_q[kMaxSlices];                  //   log2 of the size
 };
@@ -1764,6 +1765,7 @@ enum CoopWord : int {
     kCbWords = kCbRes + 2 * kWave
 };
 constexpr int64_t kCbDone = -1;
+static_assert(128 + kCbWords <= kNodeExtra, "a representation's node-pool share holds the cooperation block");
 
 DEV int64_t cb_ld(int64_t* cb, int w) {
     return __hip_atomic_load(cb + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2120,6 +2122,141 @@ DEV void dstqds_values(const double* D, const double* L, int64_t n, double tau, 
     }
 }
 
+// Division-free forms of both passes, with the pair (u, v) of negcount_rep
+// (s_i = u_i / v_i):
+//     w_i = d_i v_i + u_i,   d+_i = w_i / v_i,
+//     u_{i+1} = u_i (d_i l_i^2) - tau w_i,   v_{i+1} = w_i,
+// two dependent fused multiply-adds per row where the quotient form has a
+// reciprocal and four corrections on the chain.  The recurrence carries the
+// roundings of the quotient form's s, less the quotient's; the values pass
+// rounds d+ = w / v and l+ = (d l) / d+ once each as it writes them, a
+// relative change of one unit roundoff in each output element, inside what
+// the mixed relative error analysis of the transform (Sec. 3.2.3) allows.  A
+// lane's element growth max |d+| (and the smallest |d+|) come from the
+// hardware reciprocal of v, off the chain, good to about 2^-22 -- ample to
+// compare candidates.  (u, v) entering each 64-row tile is kept, u and v in
+// two [tile][lane] arrays, and the pair is scaled by a power of two after
+// every 8 rows of a full tile and after every row of the last, partial one:
+// the same schedule in both passes, so that the values pass reproduces the
+// winner's w and v bit for bit.
+//
+// A lane's result holds within the bounds of negcount_rep (data and tau,
+// every |w| and every rescaled |v| at least 2^-800) and with every |d+| at
+// least 2^-850 (so |l+| <= 2^1000).  A state that overflowed (|w| or |u|
+// past 2^1024 within 8 rows of a rescaling) means some |d+| >= 2^100: that
+// candidate is rejected.  Any other lane outside the bounds makes the caller
+// run the quotient form for the whole wave.
+struct HomFac {
+    int ok;          // the candidate exists (within the bounds)
+    int unknown;     // outside the bounds: only the quotient form can tell
+    double growth;   // max |d+|, about (ok lanes)
+};
+constexpr double kHomPivot = 0x1p-850;
+
+DEV void hom_rescale2(double& u, double& v) {
+    const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(u), fabs(v)));
+    u = __builtin_ldexp(u, -ex);
+    v = __builtin_ldexp(v, -ex);
+}
+
+DEV HomFac dstqds_select_hom(Shared& S, const double* D, const double* L, int64_t n, double tau, double* cku,
+                             double* ckv) {
+    const int l = lane_id();
+    double u = -tau, v = 1.0;
+    double mw = 1.0, gmax = 0.0, gmin = __builtin_inf();
+    bool data_ok = true;
+    auto row = [&](double d, double dll) {
+        const double w = __builtin_fma(d, v, u);
+        const double g = fabs(w) * __builtin_amdgcn_rcp(fabs(v));
+        gmax = fmax(gmax, g);
+        gmin = fmin(gmin, g);
+        const double p = u * dll;
+        u = __builtin_fma(-tau, w, p);
+        v = w;
+        mw = fmin(mw, fabs(w));
+    };
+    RepRow f = rep_fetch(D, L, 0, n);
+    int64_t tile = 0;
+    for (int64_t base = 0; base < n; base += kTile, ++tile) {
+        data_ok &= (__ballot(!rep_commit(S, f)) == 0ull);
+        cku[tile * kWave + l] = u;
+        ckv[tile * kWave + l] = v;
+        if (base + kTile < n) f = rep_fetch(D, L, base + kTile, n);
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        if (lim == kTile) {
+            dv2 cur[8], nxt[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cur[k] = QROW_DDLL(S, k);
+#pragma unroll
+            for (int g = 0; g < kTile / 8; ++g) {
+                if (g + 1 < kTile / 8) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) nxt[k] = QROW_DDLL(S, (g + 1) * 8 + k);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (g + 1 < kTile / 8) __builtin_amdgcn_s_waitcnt(kWaitLds8);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) row(cur[k].x, cur[k].y);
+                hom_rescale(u, v, mw);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+            }
+        } else {
+            for (int t = 0; t < lim; ++t) {
+                const dv2 x = QROW_DDLL(S, t);
+                row(x.x, x.y);
+                hom_rescale(u, v, mw);
+            }
+        }
+    }
+    const bool ovf = !__builtin_isfinite(u) || !__builtin_isfinite(v) || !(gmax < 0x1p1000);
+    HomFac o;
+    o.unknown = (!data_ok || !hom_sigma_ok(tau) || (!ovf && (!(mw >= kHomState) || !(gmin >= kHomPivot)))) ? 1 : 0;
+    o.ok = (!o.unknown && !ovf) ? 1 : 0;
+    o.growth = o.ok ? gmax : __builtin_inf();
+    return o;
+}
+
+// The rows of the candidate that lane c ran in dstqds_select_hom, written to
+// (Dp, Lp), the 64-row tiles going round the lanes from the kept (u, v).
+DEV void dstqds_values_hom(const double* D, const double* L, int64_t n, double tau, const double* cku,
+                           const double* ckv, int c, double* Dp, double* Lp) {
+    const int l = lane_id();
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    for (int64_t tile = l; tile < ntiles; tile += kWave) {
+        double u = cku[tile * kWave + c], v = ckv[tile * kWave + c];
+        const int64_t base = tile * kTile;
+        const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
+        for (int t0 = 0; t0 < lim; t0 += 8) {
+            double dd[8], ll[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t i = base + t0 + k;
+                dd[k] = (t0 + k < lim) ? D[i] : 0.0;
+                ll[k] = (t0 + k < lim && i < n - 1) ? L[i] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (t0 + k < lim) {
+                    const int64_t i = base + t0 + k;
+                    // the staged values of rep_commit
+                    const double dl = dd[k] * ll[k];
+                    const double dll = dl * ll[k];
+                    const double w = __builtin_fma(dd[k], v, u);
+                    const double dp = quot(recip(v), w);
+                    Dp[i] = dp;
+                    Lp[i] = quot(recip(dp), dl);
+                    const double p = u * dll;
+                    u = __builtin_fma(-tau, w, p);
+                    v = w;
+                    if (lim < kTile) hom_rescale2(u, v);
+                }
+            }
+            if (lim == kTile) hom_rescale2(u, v);
+        }
+    }
+}
+
 // T - mu I = L D L^T by Gaussian elimination without pivoting; sgn > 0
 // requires every pivot positive, sgn < 0 every pivot negative (a definite
 // root, Sec. 3.1.2).  In two passes, as for dstqds: factor_select runs one
@@ -2131,6 +2268,14 @@ DEV FacOut factor_select(Shared& S, const double* d, const double* e, int64_t n,
     const int l = lane_id();
     double dprev = 1.0, gmax = 0.0;
     int ok = 1;
+    // row 0 has beta = 0 staged, and dprev = 1 makes the quotient term an
+    // exact zero there: d_0 = alpha_0 - mu
+    auto row = [&](const QRow& x) {
+        const double dv = (x.d - mu) - quot(recip(dprev), x.dl) * x.dl;
+        ok &= (__builtin_isfinite(dv) && (sgn > 0 ? dv > 0.0 : dv < 0.0)) ? 1 : 0;
+        gmax = fmax(gmax, fabs(dv));
+        dprev = dv;
+    };
     RepRow f = T_fetch(d, e, 0, n, sc);
     int64_t tile = 0;
     for (int64_t base = 0; base < n; base += kTile, ++tile) {
@@ -2138,13 +2283,24 @@ DEV FacOut factor_select(Shared& S, const double* d, const double* e, int64_t n,
         ckp[tile * kWave + l] = dprev;
         if (base + kTile < n) f = T_fetch(d, e, base + kTile, n, sc);
         const int lim = (int)((n - base) < kTile ? (n - base) : kTile);
-        for (int t = 0; t < lim; ++t) {
-            const int64_t i = base + t;
-            const QRow x = S.tr[t];
-            const double dv = (i == 0) ? x.d - mu : (x.d - mu) - quot(recip(dprev), x.dl) * x.dl;
-            ok &= (__builtin_isfinite(dv) && (sgn > 0 ? dv > 0.0 : dv < 0.0)) ? 1 : 0;
-            gmax = fmax(gmax, fabs(dv));
-            dprev = dv;
+        if (lim == kTile) {
+            // rows read kAhead ahead of the recurrence, as in dstqds_select
+            QRow cur[kAhead], nxt[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) cur[u] = S.tr[u];
+#pragma unroll
+            for (int g = 0; g < kTile / kAhead; ++g) {
+                if (g + 1 < kTile / kAhead) {
+#pragma unroll
+                    for (int u = 0; u < kAhead; ++u) nxt[u] = S.tr[(g + 1) * kAhead + u];
+                }
+#pragma unroll
+                for (int u = 0; u < kAhead; ++u) row(cur[u]);
+#pragma unroll
+                for (int u = 0; u < kAhead; ++u) cur[u] = nxt[u];
+            }
+        } else {
+            for (int t = 0; t < lim; ++t) row(S.tr[t]);
         }
     }
     FacOut o;
@@ -2381,7 +2537,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     }
     // root shift mu: just outside either end, so that T - mu I is definite
     // (lane 0 the left candidate, lane 1 the right one)
-    const int64_t off = arena_alloc(P, 4 * n + 128);
+    const int64_t off = arena_alloc(P, 4 * n + kNodeExtra);
     if (off < 0) return;
     double* C0 = P.arena + off;
     double* ckp = P.arena + off + 2 * n;   // the selection's checkpoints
@@ -2567,13 +2723,14 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     const double* L = D + n;
     const int64_t sb = blk.row0 - 1;
     // the new representation's D+ and L+, then the selection's checkpoints
-    // (at most n + 64 doubles), then the block of the cooperative end
+    // (u and v, n + 64 doubles each), then the block of the cooperative end
     // refinement
-    const int64_t off = arena_alloc(P, 4 * n + 128);
+    const int64_t off = arena_alloc(P, 4 * n + kNodeExtra);
     if (off < 0) return;
     double* Cn = P.arena + off;
-    double* cks = Cn + 2 * n;
-    const int64_t cboff = off + 3 * n + 64;   // kCbWords <= n + 64 words are left for n >= kCoopMinRows
+    double* cku = Cn + 2 * n;
+    double* ckv = Cn + 3 * n + 64;
+    const int64_t cboff = off + 4 * n + 128;
     // 1. the cluster's end eigenvalues to full accuracy (Alg. 3.8, first step)
     if (l < 2) {
         const int j = (l == 0) ? p : q;
@@ -2647,29 +2804,54 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         const double del = dmin * pow(dmax / dmin, frac);
         mytau = side ? tau_r0 + del : tau_l0 - del;
     }
-    const FacOut f = dstqds_select(S, D, L, n, mytau, cks);
+    // the division-free form first; the quotient form when it cannot tell for
+    // some candidate, or when no candidate passed and one was rejected for an
+    // overflow (the least growth must then be known for every candidate)
+    const bool mine = l < 2 * T;
+    const HomFac hf = dstqds_select_hom(S, D, L, n, mytau, cku, ckv);
+    FacOut f;
+    f.ok = hf.ok;
+    f.growth = hf.growth;
+    bool quot_form = wave_or((mine && hf.unknown) ? 1 : 0) != 0;
+    if (quot_form) f = dstqds_select(S, D, L, n, mytau, cku);
     steps += 2 * n * T;
-    double best = __builtin_inf(), best_tau = 0.0;
-    int chosen = -1, best_lane = 0;
-    double tau = 0.0, chosen_growth = 0.0;
-    for (int t = 0; t < T; ++t) {
-        const int ok0 = __shfl(f.ok, 2 * t), ok1 = __shfl(f.ok, 2 * t + 1);
-        const double g0 = __shfl(f.growth, 2 * t), g1 = __shfl(f.growth, 2 * t + 1);
-        const double t0 = __shfl(mytau, 2 * t), t1 = __shfl(mytau, 2 * t + 1);
-        int pick = -1;
-        if (ok0 && ok1) pick = (g1 < g0) ? 1 : 0;
-        else if (ok0) pick = 0;
-        else if (ok1) pick = 1;
-        if (pick < 0) continue;
-        const double g = pick ? g1 : g0;
-        const double tp = pick ? t1 : t0;
-        if (g < best) { best = g; best_tau = tp; best_lane = 2 * t + pick; }
-        if (g <= thresh && chosen < 0) {
-            chosen = 2 * t + pick;
-            tau = tp;
-            chosen_growth = g;
+    double best, best_tau;
+    int chosen, best_lane;
+    double tau, chosen_growth;
+    auto pick = [&]() {
+        best = __builtin_inf();
+        best_tau = 0.0;
+        chosen = -1;
+        best_lane = 0;
+        tau = 0.0;
+        chosen_growth = 0.0;
+        for (int t = 0; t < T; ++t) {
+            const int ok0 = __shfl(f.ok, 2 * t), ok1 = __shfl(f.ok, 2 * t + 1);
+            const double g0 = __shfl(f.growth, 2 * t), g1 = __shfl(f.growth, 2 * t + 1);
+            const double t0 = __shfl(mytau, 2 * t), t1 = __shfl(mytau, 2 * t + 1);
+            int pk = -1;
+            if (ok0 && ok1) pk = (g1 < g0) ? 1 : 0;
+            else if (ok0) pk = 0;
+            else if (ok1) pk = 1;
+            if (pk < 0) continue;
+            const double g = pk ? g1 : g0;
+            const double tp = pk ? t1 : t0;
+            if (g < best) { best = g; best_tau = tp; best_lane = 2 * t + pk; }
+            if (g <= thresh && chosen < 0) {
+                chosen = 2 * t + pk;
+                tau = tp;
+                chosen_growth = g;
+            }
         }
+    };
+    pick();
+    if (chosen < 0 && !quot_form && wave_or((mine && !hf.ok) ? 1 : 0)) {
+        quot_form = true;
+        f = dstqds_select(S, D, L, n, mytau, cku);
+        steps += 2 * n * T;
+        pick();
     }
+    if (quot_form && l == 0) S.redo_fac += 1;
     int unverified = 0;
     if (chosen < 0) {
         if (!(best < __builtin_inf())) {
@@ -2684,7 +2866,8 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     }
     // the checkpoints of lane `chosen` go to every lane
     __syncthreads();
-    dstqds_values(D, L, n, tau, cks, chosen, Cn, Cn + n);
+    if (quot_form) dstqds_values(D, L, n, tau, cku, chosen, Cn, Cn + n);
+    else dstqds_values_hom(D, L, n, tau, cku, ckv, chosen, Cn, Cn + n);
     steps += n;
     const int id = new_node(P);
     if (id < 0) return;
@@ -2959,6 +3142,7 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
     if (l == 0) {
         S.redo = 0;
         S.redo_sturm = 0;
+        S.redo_fac = 0;
     }
     for (;;) {
         if (l == 0) {
@@ -3042,6 +3226,7 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
     add_stat(&P.ctl->n_single, nsingle);
     add_stat(&P.ctl->n_nan, (int64_t)S.redo);
     add_stat(&P.ctl->n_sturm, (int64_t)S.redo_sturm);
+    add_stat(&P.ctl->n_fac_quot, (int64_t)S.redo_fac);
 }
 
 // Resets the control block and the queue cells (no memset nodes, so that the

@@ -255,7 +255,7 @@ def test_grad_config5_n8192_oracle_fd_and_identities(orc):
     returned), pairs closer than 1e-8 ||T|| masked on both sides: the
     gradient must agree to 1e-6 of its largest entry.
 
-    Against central differences: 64 sampled coordinates plus one seeded unit
+    Against central differences: 128 sampled coordinates plus one seeded unit
     direction, Richardson values from h = 1e-6 and h/2 = 5e-7 (see _fd_check),
     with the perturbed solves' vectors sign-aligned to the unperturbed ones;
     the directions whose value the loss's rounding noise decides are counted
@@ -315,6 +315,12 @@ def test_grad_config5_n8192_oracle_fd_and_identities(orc):
     x0 = np.concatenate([d0, e0])
     rng = np.random.default_rng(21)
     coords = np.concatenate([rng.choice(n, 32, replace=False), n + rng.choice(n - 1, 32, replace=False)])
+    # 64 more coordinates (another generator, so the first 64 stay the same):
+    # at n = 8192 the rounding noise of the forward decides most quotients, and
+    # enough must be left to judge by
+    rng2 = np.random.default_rng(22)
+    coords = np.concatenate([coords, rng2.choice(np.setdiff1d(np.arange(n), coords), 32, replace=False),
+                             n + rng2.choice(np.setdiff1d(np.arange(n - 1), coords[32:] - n), 32, replace=False)])
     dirs = [np.eye(1, 2 * n - 1, k)[0] for k in coords]
     v = rng.standard_normal(2 * n - 1)
     dirs.append(v / np.linalg.norm(v))
