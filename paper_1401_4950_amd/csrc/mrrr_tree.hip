@@ -1630,9 +1630,15 @@ DEV void chunk_maxbits(int bits, int* mb) {
 }
 DEV int slice_q(const int* mb, double Pb, const double* bpp, const int* cf, int qmin, int qmax) {
     // bpp[k] and cf[k] are for slices of 64 >> k members, i.e. q = 6 - k;
-    // cf passes confirm the members' unverified bracket ends first
-    int q = qmax;
-    while (q > qmin && (double)mb[q] > (Pb - (double)cf[6 - q]) * bpp[6 - q]) --q;
+    // cf passes confirm the members' unverified bracket ends first.  The
+    // largest fitting q in (qmin, qmax], else qmin; every block size is
+    // tested (constant indices keep the arrays in registers)
+    int q = qmin;
+#pragma unroll
+    for (int k = 1; k <= 6; ++k) {
+        const bool fit = (double)mb[k] <= (Pb - (double)cf[6 - k]) * bpp[6 - k];
+        q = (k > qmin && k <= qmax && fit) ? k : q;
+    }
     return q;
 }
 
@@ -1659,6 +1665,7 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
     int P0 = best_cf + (int)ceil((double)maxbits / best_bpp);
     if (P0 < 1) P0 = 1;
     constexpr int kTry = 8;
+    constexpr int kAheadChunks = 4;   // chunks whose needs are loaded together
     int Pb = 0, ns = 0;
     for (int round = 0; round < 4 && Pb == 0; ++round) {
         int pbk[kTry], nsk[kTry];
@@ -1666,15 +1673,24 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
             pbk[t] = P0 + (P0 * t) / 4 + t;
             nsk[t] = 0;
         }
-        for (int base = a; base <= b; base += kWave) {
-            const int j = base + l;
-            const bool in = j <= b;
-            int mb[7];
-            chunk_maxbits(in ? (int)P.need[sb + j] : 0, mb);
+        for (int base = a; base <= b; base += kAheadChunks * kWave) {
+            int nd[kAheadChunks];
 #pragma unroll
-            for (int t = 0; t < kTry; ++t) {
-                const int q = slice_q(mb, (double)pbk[t], bpp, cf, qmin, qmax);
-                nsk[t] += __popcll(__ballot(in && (l & ((1 << q) - 1)) == 0));
+            for (int k = 0; k < kAheadChunks; ++k) {
+                const int j = base + k * kWave + l;
+                nd[k] = (j <= b) ? (int)P.need[sb + j] : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kAheadChunks; ++k) {
+                if (base + k * kWave > b) break;
+                const bool in = base + k * kWave + l <= b;
+                int mb[7];
+                chunk_maxbits(nd[k], mb);
+#pragma unroll
+                for (int t = 0; t < kTry; ++t) {
+                    const int q = slice_q(mb, (double)pbk[t], bpp, cf, qmin, qmax);
+                    nsk[t] += __popcll(__ballot(in && (l & ((1 << q) - 1)) == 0));
+                }
             }
         }
         for (int t = 0; t < kTry && Pb == 0; ++t) {
@@ -1689,11 +1705,23 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
     // list the slices in LDS and push the list whenever it fills (one wait
     // for free cells per 64 slices instead of one per 64-member chunk)
     int listed = 0;
+    int nd[kAheadChunks];
     for (int base = a; base <= b; base += kWave) {
+        const int kc = ((base - a) / kWave) % kAheadChunks;
+        if (kc == 0) {
+#pragma unroll
+            for (int u = 0; u < kAheadChunks; ++u) {
+                const int ju = base + u * kWave + l;
+                nd[u] = (ju <= b) ? (int)P.need[sb + ju] : 0;
+            }
+        }
         const int j = base + l;
         const bool in = j <= b;
         int mb[7];
-        chunk_maxbits(in ? (int)P.need[sb + j] : 0, mb);
+        int ndk = nd[0];
+#pragma unroll
+        for (int u = 1; u < kAheadChunks; ++u) ndk = (kc == u) ? nd[u] : ndk;
+        chunk_maxbits(ndk, mb);
         const int q = slice_q(mb, (double)Pb, bpp, cf, qmin, qmax);
         const bool st = in && (l & ((1 << q) - 1)) == 0;
         const uint64_t sm = __ballot(st);
