@@ -387,7 +387,14 @@ def main(argv=None):
                            "tree_ms": float(np.median([st["tree_ms"] for _, st in rs])),
                            "qd_steps": int(rs[0][1]["qd_steps"]), "dmax": int(rs[0][1]["dmax"]),
                            "n_nodes": int(rs[0][1]["n_nodes"]),
-                           "largest_cluster": int(rs[0][1]["largest_cluster"])}
+                           "largest_cluster": int(rs[0][1]["largest_cluster"]),
+                           # representations accepted without passing max|D+| <= 8 spdiam, those of
+                           # them checked (and failed) for conditional element growth, and the
+                           # returned status (1 = MRRR_WARN_UNVERIFIED)
+                           "unverified": int(rs[0][1]["n_unverified_rrr"]),
+                           "cond_checked": int(rs[0][1]["n_cond_checked"]),
+                           "cond_failed": int(rs[0][1]["n_cond_failed"]),
+                           "status": int(rs[0][1].get("status", 0))}
     out = {
         "metric": "FP64 eigenpairs/s at n=20000 all pairs; batched & fwd+bwd speedup vs plain",
         "value": value,

@@ -103,9 +103,14 @@ def batched_layout(n_offsets, z_offsets=None):
 
 
 def last_stats() -> dict:
-    """Statistics of the most recent solve on this thread."""
+    """Statistics of the most recent solve on this thread, with the status it
+    returned (0, or MRRR_WARN_UNVERIFIED = 1) under "status"."""
     st = getattr(_tls, "stats", None)
-    return st.as_dict() if st is not None else {}
+    if st is None:
+        return {}
+    out = st.as_dict()
+    out["status"] = int(getattr(_tls, "status", 0))
+    return out
 
 
 def _options(options, jobz):
@@ -168,6 +173,7 @@ def eigh_tridiagonal(d, e, select="a", select_range=None, eigvals_only=False, op
     code = getattr(_lib.load(), entry)(h, n, _ptr(d), _ptr(e), rng, vl, vu, il, iu, ctypes.byref(o),
                                        ctypes.byref(m), _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(st))
     _tls.stats = st
+    _tls.status = code
     _lib.check(code, entry)
     k = m.value
     w = w[:k]
@@ -204,6 +210,7 @@ def eigh_symmetric(A, select="a", select_range=None, eigvals_only=False, options
     code = _lib.load().mrrr_dsyevr(h, n, _ptr(A), max(n, 1), rng, vl, vu, il, iu, ctypes.byref(o), ctypes.byref(m),
                                    _ptr(w), _ptr(Zbuf), max(n, 1), ctypes.byref(st))
     _tls.stats = st
+    _tls.status = code
     _lib.check(code, "mrrr_dsyevr")
     k = m.value
     w = w[:k]
@@ -257,6 +264,7 @@ def eigh_tridiagonal_batched(d_cat, e_cat, n_offsets, z_offsets=None, eigvals_on
     code = _lib.load().mrrr_dstemr_batched(h, batch, arr, _ptr(d_cat), _ptr(e_cat), zarr, ctypes.byref(o),
                                            _ptr(w_cat), _ptr(Z_cat), ctypes.byref(st))
     _tls.stats = st
+    _tls.status = code
     _lib.check(code, "mrrr_dstemr_batched")
     return (w_cat, Z_cat) if not eigvals_only else w_cat
 
