@@ -99,6 +99,13 @@ typedef struct {
                                 bound is (k_elg / 3) n spdiam; 0 switches the
                                 check off (every representation that failed the
                                 element-growth bound then stays unverified) */
+    int32_t bundle_helpers;  /* 1 (default): the worker of a singleton bundle on
+                                a representation of 4096 rows or more takes an
+                                idle worker, when there is one, to share its
+                                twisted factorisations and eigenvector solve
+                                (the results are the same bit for bit);
+                                0: never */
+    int32_t pad2;
 } mrrr_options_t;
 
 /* One record per executed device task (the per-task timeline of the
@@ -106,7 +113,9 @@ typedef struct {
  * stats->n_tasks tells how many tasks ran (records beyond trace_cap are
  * dropped). */
 typedef struct {
-    int32_t type;    /* 1 root, 2 refinement slice, 3 cluster, 4 singleton bundle */
+    int32_t type;    /* 1 root, 2 refinement slice, 3 cluster, 4 singleton bundle,
+                        5 helper of a cluster's end refinement, 6 helper of a
+                        singleton bundle */
     int32_t worker;  /* workgroup (wavefront) index */
     int32_t node;    /* representation the task worked on (root: block) */
     int32_t depth;   /* its depth in the representation tree */

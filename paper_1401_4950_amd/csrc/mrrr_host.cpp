@@ -144,6 +144,8 @@ extern "C" void mrrr_default_options(mrrr_options_t* o) {
     o->arena_scale = 1.0;
     o->check_tol = 20.0;
     o->cond_growth_k = 10.0;
+    o->bundle_helpers = 1;
+    o->pad2 = 0;
 }
 
 extern "C" const char* mrrr_status_string(int s) {
@@ -306,6 +308,7 @@ void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int worker
     P.max_depth = o.max_depth;
     P.slice_min = std::max(1, o.slice_min);
     P.sign_conv = o.sign_convention;
+    P.assist = o.bundle_helpers != 0 ? 1 : 0;
     P.nworkers = workers;
     P.timeout_ticks = (uint64_t)std::max(1.0, o.timeout_s * wall_khz * 1000.0);
     P.trace = (o.trace && o.trace_cap > 0) ? static_cast<TraceRec*>(o.trace) : nullptr;

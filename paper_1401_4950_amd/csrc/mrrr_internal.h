@@ -31,7 +31,8 @@ enum TaskType : int32_t {
     kTaskRefine = 2,   // refine a slice of one node's eigenvalue brackets
     kTaskCluster = 3,  // new RRR for a cluster (Alg. 3.8), then refine its members
     kTaskSingle = 4,   // bundle of singletons of one node (Alg. 4.3 + Alg. 3.7)
-    kTaskHelp = 5      // idle worker lending its lanes to a cluster's end refinement
+    kTaskHelp = 5,     // idle worker lending its lanes to a cluster's end refinement
+    kTaskAssist = 6    // idle worker sharing a singleton bundle's passes
 };
 
 enum RefineMode : int32_t { kModeClass = 0, kModeFull = 1 };
@@ -207,7 +208,8 @@ struct Params {
     int64_t total_rows;
     double gaptol, rtol, xi;
     uint64_t seed;
-    int32_t max_rqi, max_tries, max_depth, slice_min, sign_conv, pad_o;
+    int32_t max_rqi, max_tries, max_depth, slice_min, sign_conv;
+    int32_t assist;       // singleton bundles may take a helper (same results)
     uint64_t timeout_ticks;
     TraceRec* trace;
     int64_t trace_cap;

@@ -923,10 +923,16 @@ DEV void row_data(const double* D, const double* L, int64_t n, int64_t i, double
     dl2 = dl * dl;
 }
 
-DEV TwistOut twisted_hom(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
-                         const CkPtr& ck, int64_t& steps) {
-    TwistOut o;
-    // ---- forward
+// The forward half of twisted_hom: the stationary transform over all rows
+// with its checkpoints (u, v, E every kCkb rows), the sign count, the
+// smallest |w| and the last row's w and v.
+struct TwFwd {
+    double u, v, E, mw, wl, vl;
+    int cnt;
+    bool data_ok;
+};
+DEV TwFwd tw_forward(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live, const CkPtr& ck,
+                     int64_t& steps) {
     double u = -lam, v = 1.0, E = 1.0, mw = 1.0;
     double wl = 0.0, vl = 1.0;     // w_{n-1}, v_{n-1}
     unsigned B = 0, Bold = 0;
@@ -999,6 +1005,74 @@ DEV TwistOut twisted_hom(Shared& S, const double* D, const double* L, int64_t n,
         }
     }
     steps += n;
+    TwFwd o;
+    o.u = u;
+    o.v = v;
+    o.E = E;
+    o.mw = mw;
+    o.wl = wl;
+    o.vl = vl;
+    o.cnt = cnt;
+    o.data_ok = data_ok;
+    return o;
+}
+
+// The end of twisted_hom: gamma_r, h_r and g_r at the twist index r alone
+// (IEEE quotients), from the checkpoints of both transforms; `bfin` tells
+// whether the backward transform's final state was finite, `mw` is the
+// smallest |w| and |omega| of both.
+DEV TwistOut tw_at_r(const double* D, const double* L, int64_t n, double lam, bool live, const CkPtr& ck, int r,
+                     const TwFwd& f, bool bfin, double mw) {
+    TwistOut o;
+    const double wl = f.wl, vl = f.vl, E = f.E;
+    double gam = wl / vl, hr = E / (vl * vl), gr = 1.0;
+    if (live && r < n - 1) {
+        const int64_t c = r / kCkb;
+        double uu = ck.at(c, 0), vv = ck.at(c, 1), EE = ck.at(c, 2);
+        double d, dll, dl, dl2;
+        for (int64_t i = c * kCkb; i < r; ++i) {
+            row_data(D, L, n, i, d, dll, dl, dl2);
+            const double w = __builtin_fma(d, vv, uu);
+            const double p = uu * dll;
+            uu = __builtin_fma(-lam, w, p);
+            EE = __builtin_fma(dl2, EE, w * w);
+            vv = w;
+            if ((i & 7) == 7) hom_fwd_scale(uu, vv, EE);
+        }
+        const int64_t b1 = (c * kCkb + kCkb) < (n - 1) ? (c * kCkb + kCkb) : (n - 1);
+        double xx = ck.at(c, 3), yy = ck.at(c, 4), FF = ck.at(c, 5);
+        for (int64_t i = b1 - 1; i > r; --i) {
+            row_data(D, L, n, i, d, dll, dl, dl2);
+            const double om = __builtin_fma(dll, yy, xx);
+            xx = __builtin_fma(-lam, om, d * xx);
+            FF = __builtin_fma(dl2, FF, om * om);
+            yy = om;
+            if ((i & 7) == 0) hom_bwd_scale(xx, yy, FF);
+        }
+        row_data(D, L, n, r, d, dll, dl, dl2);
+        const double om = __builtin_fma(dll, yy, xx);
+        const double m = d * xx;
+        gam = __builtin_fma(uu, om, m * vv) / (vv * om);
+        hr = EE / (vv * vv);
+        gr = __builtin_fma(dl2, FF, om * om) / (om * om);
+    }
+    o.neg = f.cnt;
+    o.r = r;
+    o.gam = gam;
+    o.nrm2 = hr + gr - 1.0;
+    const bool fin = __builtin_isfinite(f.u) && __builtin_isfinite(f.v) && __builtin_isfinite(E) && bfin &&
+                     __builtin_isfinite(o.nrm2) && __builtin_isfinite(gam);
+    o.bad = (live && (!f.data_ok || !hom_sigma_ok(lam) || !(mw >= kHomState) || !fin || !(hr >= 0.5) ||
+                      !(gr >= 0.5))) ? 1 : 0;
+    o.guarded = 0;
+    return o;
+}
+
+DEV TwistOut twisted_hom(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
+                         const CkPtr& ck, int64_t& steps) {
+    const TwFwd fw = tw_forward(S, D, L, n, lam, live, ck, steps);
+    const double wl = fw.wl, vl = fw.vl;
+    double mw = fw.mw;
     // ---- backward, with the argmin of |gamma|
     const int64_t cl = (n - 1) / kCkb;
     double x = D[n - 1] - lam, y = 1.0, F = 1.0;
@@ -1081,49 +1155,8 @@ DEV TwistOut twisted_hom(Shared& S, const double* D, const double* L, int64_t n,
         }
     }
     steps += 2 * n;
-    // ---- gamma_r, h_r, g_r at r alone, IEEE quotients
-    double gam = wl / vl, hr = E / (vl * vl), gr = 1.0;
-    if (live && r < n - 1) {
-        const int64_t c = r / kCkb;
-        double uu = ck.at(c, 0), vv = ck.at(c, 1), EE = ck.at(c, 2);
-        double d, dll, dl, dl2;
-        for (int64_t i = c * kCkb; i < r; ++i) {
-            row_data(D, L, n, i, d, dll, dl, dl2);
-            const double w = __builtin_fma(d, vv, uu);
-            const double p = uu * dll;
-            uu = __builtin_fma(-lam, w, p);
-            EE = __builtin_fma(dl2, EE, w * w);
-            vv = w;
-            if ((i & 7) == 7) hom_fwd_scale(uu, vv, EE);
-        }
-        const int64_t b1 = (c * kCkb + kCkb) < (n - 1) ? (c * kCkb + kCkb) : (n - 1);
-        double xx = ck.at(c, 3), yy = ck.at(c, 4), FF = ck.at(c, 5);
-        for (int64_t i = b1 - 1; i > r; --i) {
-            row_data(D, L, n, i, d, dll, dl, dl2);
-            const double om = __builtin_fma(dll, yy, xx);
-            xx = __builtin_fma(-lam, om, d * xx);
-            FF = __builtin_fma(dl2, FF, om * om);
-            yy = om;
-            if ((i & 7) == 0) hom_bwd_scale(xx, yy, FF);
-        }
-        row_data(D, L, n, r, d, dll, dl, dl2);
-        const double om = __builtin_fma(dll, yy, xx);
-        const double m = d * xx;
-        gam = __builtin_fma(uu, om, m * vv) / (vv * om);
-        hr = EE / (vv * vv);
-        gr = __builtin_fma(dl2, FF, om * om) / (om * om);
-    }
-    o.neg = cnt;
-    o.r = r;
-    o.gam = gam;
-    o.nrm2 = hr + gr - 1.0;
-    const bool fin = __builtin_isfinite(u) && __builtin_isfinite(v) && __builtin_isfinite(E) &&
-                     __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(F) &&
-                     __builtin_isfinite(o.nrm2) && __builtin_isfinite(gam);
-    o.bad = (live && (!data_ok || !hom_sigma_ok(lam) || !(mw >= kHomState) || !fin || !(hr >= 0.5) ||
-                      !(gr >= 0.5))) ? 1 : 0;
-    o.guarded = 0;
-    return o;
+    return tw_at_r(D, L, n, lam, live, ck, r, fw,
+                   __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(F), mw);
 }
 
 // Alg. 3.7's N_r^T z = e_r in the division-free form (see twisted_hom), from
@@ -1131,16 +1164,19 @@ DEV TwistOut twisted_hom(Shared& S, const double* D, const double* L, int64_t n,
 // block the states are recomputed in registers, then the solution runs
 // through the block.  Values scaled by `scale` go to zcol[row] when `write`;
 // the sum of squares is returned.
+// `part`: 0 the whole vector; 1 the rows below the twist (r+1 .. n-1) alone;
+// 2 the rows above it and z_r (the two parts are independent; a bundle's
+// helper takes part 1).
 DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live, int r,
-                            double scale, const CkPtr& ck, double* zcol, bool write, int64_t& steps) {
+                            double scale, const CkPtr& ck, double* zcol, bool write, int part, int64_t& steps) {
     // The rows of one block run without branches that depend on r: every lane
     // steps through every row and keeps its running product only on the rows
     // of its own half; the stores and the sum of squares are masked.
-    double ss = live ? 1.0 : 0.0;
+    double ss = (live && part != 1) ? 1.0 : 0.0;
     const int64_t cl = (n - 1) / kCkb;
     // ---- upward: z_k = yh_k X_k for k = r+1 .. n-1
     double X = 0.0, dlprev = 0.0;
-    {
+    if (part != 2) {
         double x_next = live ? ck.at(0, 3) : 0.0, y_next = live ? ck.at(0, 4) : 1.0;
         RepRow fu = rep_fetch(D, L, 0, n);
         for (int64_t tb = 0; tb < n; tb += kTile) {
@@ -1211,7 +1247,7 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
         }
     }
     // ---- downward: z_i = v_i Y_i for i = r-1 .. 0
-    {
+    if (part != 1) {
         double Y = 0.0;
         double u_next = live ? ck.at(cl, 0) : 0.0, v_next = live ? ck.at(cl, 1) : 1.0;
         const int64_t last_tile = ((n - 1) / kTile) * kTile;
@@ -1282,8 +1318,8 @@ DEV double solve_vector_hom(Shared& S, const double* D, const double* L, int64_t
             }
         }
     }
-    if (live && write) zcol[r] = scale;
-    steps += 2 * n;
+    if (live && write && part != 1) zcol[r] = scale;
+    steps += (part == 0) ? 2 * n : n;
     return ss;
 }
 
@@ -1450,7 +1486,7 @@ DEV double solve_vector_impl(Shared& S, const double* D, const double* L, int64_
 // pass, which rewrites every entry of its column.
 DEV double solve_vector(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live, int r,
                         double scale, const CkPtr& ck, double* zcol, bool write, bool guarded, int64_t& steps) {
-    double ss = solve_vector_hom(S, D, L, n, lam, live && !guarded, r, scale, ck, zcol, write, steps);
+    double ss = solve_vector_hom(S, D, L, n, lam, live && !guarded, r, scale, ck, zcol, write, 0, steps);
     const bool redo = live && (guarded || __builtin_isnan(ss));
     if (wave_or(redo ? 1 : 0)) {
         const double sg = solve_vector_impl<true>(S, D, L, n, lam, redo, r, scale, ck, zcol, write, steps);
@@ -3021,6 +3057,424 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     push_slices(S, P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes, maxbits);
 }
 
+// ------------------------------------- a helper for a singleton bundle
+//
+// When idle workers are about (the last bundles of a solve), a bundle's
+// worker (the leader) takes one of them as a helper, and the two waves share
+// each twisted factorisation and the eigenvector solve, in the same arithmetic
+// as the one-wave forms, so that every value comes out bit for bit the same:
+//   1. the leader runs the forward transform (tw_forward) while the helper
+//      runs the backward one over all rows, keeping its checkpoints
+//      (tw_backward_plain);
+//   2. the 16-row blocks are split at a tile boundary: each wave replays both
+//      transforms of its blocks from the checkpoints and ranks |gamma| there
+//      (tw_gamma_blocks); the lower index wins ties, as in the one-wave scan;
+//   3. the eigenvector's part below the twist and its part above it are
+//      written by the two waves (solve_vector_hom's two halves).
+// The leader publishes its lanes' data in a block of the node pool and a
+// command word; the helper answers with an acknowledgement (release /
+// acquire at agent scope).
+constexpr int64_t kAssistMinRows = 4096;   // shorter transforms are not worth sharing
+enum AsWord : int {
+    kAsGen = 0,     // (sequence << 8) | command; kAsDone once the leader is finished
+    kAsJoin,        // 0 open, 1 a helper joined, 2 closed without one
+    kAsAck,         // the helper's last finished sequence << 8 | command
+    kAsNode,        // the node whose representation is used
+    kAsLive,        // lanes that take part (64-bit mask)
+    kAsHalf,        // the first block of the helper's share (a multiple of 4)
+    kAsStride,      // checkpoint stride of the bundle's problem
+    kAsLam = 8,                 // [64] shifts (bits of doubles)
+    kAsCk = kAsLam + kWave,     // [64] checkpoint column offsets in P.ck
+    kAsR = kAsCk + kWave,       // [64] twist indices
+    kAsScale = kAsR + kWave,    // [64] eigenvector scales
+    kAsZ = kAsScale + kWave,    // [64] column offsets in P.Z
+    kAsBest = kAsZ + kWave,     // [64] best |gamma| (in: gamma_{n-1}; out: the helper's)
+    kAsRb = kAsBest + kWave,    // [64] its row
+    kAsMw = kAsRb + kWave,      // [64] the helper's smallest |omega| / its sum of squares
+    kAsFin = kAsMw + kWave,     // [64] the helper's final backward state finite
+    kAsWords = kAsFin + kWave
+};
+enum AsCmd : int { kCmdBwd = 1, kCmdGamma = 2, kCmdVecUp = 3 };
+constexpr int64_t kAsDone = -1;
+
+struct Assist {
+    int64_t* cb;
+    int64_t gen;
+    bool on;
+};
+
+DEV double as_ldd(int64_t* cb, int w) { return __longlong_as_double((long long)cb_ld(cb, w)); }
+DEV void as_std(int64_t* cb, int w, double x) { cb_st(cb, w, (int64_t)__double_as_longlong(x)); }
+
+// Every lane's stores out, then the command (release).
+DEV void as_issue(Assist& as, int cmd) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    as.gen = (((as.gen >> 8) + 1) << 8) | cmd;
+    if (lane_id() == 0) __hip_atomic_store(as.cb + kAsGen, as.gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Until the helper has acknowledged the last command (acquire); false on an
+// error or the watchdog.
+DEV bool as_wait(const Params& P, Assist& as) {
+    int stop = 0;
+    if (lane_id() == 0) {
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(as.cb + kAsAck, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != as.gen) {
+            if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                wall_clock64() - t0 > P.timeout_ticks) {
+                stop = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+    if (__shfl(stop, 0)) {
+        set_error(P, kErrTimeout);
+        return false;
+    }
+    return true;
+}
+
+// Takes a helper for a bundle of node `node_id` if an idle worker joins
+// within 40 us (the lanes' checkpoint columns at ck_off).  Tried at the start
+// of every Rayleigh-quotient step and before the eigenvector solve until one
+// joins: the result does not depend on when it does.  The block comes from
+// the node pool once per bundle and serves every try.
+DEV void assist_try(const Params& P, Assist& as, int node_id, int64_t n, int64_t ck_stride, int64_t ck_off) {
+    if (as.on || !P.assist || n < kAssistMinRows || coop_helpers(P) <= 0) return;
+    if (as.cb == nullptr) {
+        const int64_t off = arena_alloc(P, kAsWords);
+        if (off < 0) return;
+        as.cb = reinterpret_cast<int64_t*>(P.arena + off);
+    }
+    int64_t* cb = as.cb;
+    if (lane_id() == 0) {
+        cb_st(cb, kAsGen, 0);
+        cb_st(cb, kAsAck, 0);
+        cb_st(cb, kAsNode, node_id);
+        cb_st(cb, kAsStride, ck_stride);
+        cb_st(cb, kAsJoin, 0);
+    }
+    cb_st(cb, kAsCk + lane_id(), ck_off);
+    as.gen = 0;
+    const int64_t off = reinterpret_cast<double*>(cb) - P.arena;
+    Task t;
+    t.type = kTaskAssist;
+    t.node = node_id;
+    t.a = (int32_t)(uint32_t)((uint64_t)off & 0xffffffffull);
+    t.b = (int32_t)(uint32_t)((uint64_t)off >> 32);
+    if (!push_one(P, kQRefine, t)) return;   // its release publishes the block
+    int64_t st = 0;
+    if (lane_id() == 0) {
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+            st = cb_ld(cb, kAsJoin);
+            if (st != 0) break;
+            if (wall_clock64() - t0 > 4000) {   // 40 us of the 100 MHz clock: close it
+                int64_t expect = 0;
+                __hip_atomic_compare_exchange_strong(cb + kAsJoin, &expect, (int64_t)2, __ATOMIC_ACQ_REL,
+                                                     __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                st = (expect == 0) ? 2 : expect;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    as.on = (__shfl(st, 0) == 1);
+}
+
+DEV void assist_close(Assist& as) {
+    if (as.on && lane_id() == 0)
+        __hip_atomic_store(as.cb + kAsGen, kAsDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    as.on = false;
+}
+
+// The backward (progressive) transform over all rows with its checkpoints,
+// in twisted_hom's arithmetic, without the ranking of gamma.  Returns the
+// smallest |omega|; `fin` whether the final state is finite.
+DEV double tw_backward_plain(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
+                             const CkPtr& ck, bool& fin, int64_t& steps) {
+    const int64_t cl = (n - 1) / kCkb;
+    double x = D[n - 1] - lam, y = 1.0, F = 1.0, mw = 1.0;
+    if (live) {
+        ck.at(cl, 3) = x;
+        ck.at(cl, 4) = y;
+        ck.at(cl, 5) = F;
+    }
+    const int64_t last_tile = ((n - 1) / kTile) * kTile;
+    RepRow fb_ = rep_fetch(D, L, last_tile, n);
+    for (int64_t tb = last_tile; tb >= 0; tb -= kTile) {
+        rep_commit(S, fb_);
+        if (tb - kTile >= 0) fb_ = rep_fetch(D, L, tb - kTile, n);
+        const int64_t cfirst = tb / kCkb;
+        const int64_t clast = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
+        for (int64_t c = clast; c >= cfirst; --c) {
+            const int64_t b0 = c * kCkb;
+            const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);   // rows [b0, b1)
+            if (b0 >= b1) continue;
+            if (c < cl && live) {
+                ck.at(c, 3) = x;
+                ck.at(c, 4) = y;
+                ck.at(c, 5) = F;
+            }
+            const int nb = (int)(b1 - b0);
+            auto run = [&](auto full_t) {
+                constexpr bool kFull = decltype(full_t)::value;
+                const int kb = (int)(b0 - tb);
+                QRow xr[kCkb];
+#pragma unroll
+                for (int t = 0; t < kCkb; ++t) xr[t] = S.tr[kFull ? kb + t : (kb + t < kTile ? kb + t : kTile - 1)];
+#pragma unroll
+                for (int t = kCkb - 1; t >= 0; --t) {
+                    if (kFull || t < nb) {
+                        const double om = __builtin_fma(xr[t].dll, y, x);
+                        const double m = xr[t].d * x;
+                        x = __builtin_fma(-lam, om, m);
+                        F = __builtin_fma(xr[t].dl2, F, om * om);
+                        y = om;
+                        mw = fmin(mw, fabs(om));
+                        if ((t & 7) == 0) hom_bwd_scale(x, y, F);
+                    }
+                }
+            };
+            if (nb == kCkb) run(std::true_type{});
+            else run(std::false_type{});
+        }
+    }
+    steps += n;
+    fin = __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(F);
+    return mw;
+}
+
+// twisted_hom's ranking of |gamma| over the blocks [c0, c1] (c0 a multiple
+// of 4), both transforms replayed from their checkpoints; best and r come in
+// as the ranking stands above block c1 and go out as it stands after c0.
+DEV void tw_gamma_blocks(Shared& S, const double* D, const double* L, int64_t n, double lam, bool live,
+                         const CkPtr& ck, int64_t c0, int64_t c1, double& best, int& r, int64_t& steps) {
+    if (c1 < c0) return;
+    const int64_t t_hi = (c1 * kCkb / kTile) * kTile, t_lo = c0 * kCkb;
+    RepRow fb_ = rep_fetch(D, L, t_hi, n);
+    // both transforms' states entering each block, loaded a block ahead
+    double un = live ? ck.at(c1, 0) : 0.0, vn = live ? ck.at(c1, 1) : 1.0;
+    double xn = live ? ck.at(c1, 3) : 0.0, yn = live ? ck.at(c1, 4) : 1.0;
+    for (int64_t tb = t_hi; tb >= t_lo; tb -= kTile) {
+        rep_commit(S, fb_);
+        if (tb - kTile >= t_lo) fb_ = rep_fetch(D, L, tb - kTile, n);
+        const int64_t cfirst = tb / kCkb;
+        const int64_t clast0 = ((tb + kTile - 1) < (n - 1) ? (tb + kTile - 1) : (n - 1)) / kCkb;
+        const int64_t clast = clast0 < c1 ? clast0 : c1;
+        for (int64_t c = clast; c >= cfirst; --c) {
+            double uu = un, vv = vn, x = xn, y = yn, F = 0.0;
+            const bool ahead = live && c - 1 >= c0;
+            un = ahead ? ck.at(c - 1, 0) : 0.0;
+            vn = ahead ? ck.at(c - 1, 1) : 1.0;
+            xn = ahead ? ck.at(c - 1, 3) : 0.0;
+            yn = ahead ? ck.at(c - 1, 4) : 1.0;
+            const int64_t b0 = c * kCkb;
+            const int64_t b1 = (b0 + kCkb) < (n - 1) ? (b0 + kCkb) : (n - 1);   // rows [b0, b1)
+            if (b0 >= b1) continue;
+            const int nb = (int)(b1 - b0);
+            auto run = [&](auto full_t) {
+                constexpr bool kFull = decltype(full_t)::value;
+                const int kb = (int)(b0 - tb);
+                QRow xr[kCkb];
+#pragma unroll
+                for (int t = 0; t < kCkb; ++t) xr[t] = S.tr[kFull ? kb + t : (kb + t < kTile ? kb + t : kTile - 1)];
+                double ur[kCkb], vr[kCkb];
+#pragma unroll
+                for (int t = 0; t < kCkb; ++t) {
+                    ur[t] = uu;
+                    vr[t] = vv;
+                    if (kFull || t < nb) {
+                        const double w = __builtin_fma(xr[t].d, vv, uu);
+                        const double p = uu * xr[t].dll;
+                        uu = __builtin_fma(-lam, w, p);
+                        vv = w;
+                        if ((t & 7) == 7) {
+                            const int ex = __builtin_amdgcn_frexp_exp(vv);
+                            uu = __builtin_ldexp(uu, -ex);
+                            vv = __builtin_ldexp(vv, -ex);
+                        }
+                    }
+                }
+                int rt = -1;
+#pragma unroll
+                for (int t = kCkb - 1; t >= 0; --t) {
+                    if (kFull || t < nb) {
+                        const double om = __builtin_fma(xr[t].dll, y, x);
+                        const double m = xr[t].d * x;
+                        const double num = __builtin_fma(ur[t], om, m * vr[t]);
+                        const double den = vr[t] * om;
+                        const double ga = fabs(num) * __builtin_amdgcn_rcp(fabs(den));
+                        const bool take = ga <= best;
+                        best = take ? ga : best;
+                        rt = take ? t : rt;
+                        x = __builtin_fma(-lam, om, m);
+                        y = om;
+                        if ((t & 7) == 0) hom_bwd_scale(x, y, F);
+                    }
+                }
+                if (rt >= 0) r = (int)b0 + rt;
+            };
+            if (nb == kCkb) run(std::true_type{});
+            else run(std::false_type{});
+        }
+    }
+    steps += (c1 - c0 + 1) * kCkb;
+}
+
+// twisted_hom shared with the helper (see above); the same result.
+DEV TwistOut twisted_split(Shared& S, const Params& P, const double* D, const double* L, int64_t n, double lam,
+                           bool live, const CkPtr& ck, Assist& as, int64_t& steps) {
+    const int l = lane_id();
+    const int64_t cl = (n - 1) / kCkb;
+    as_std(as.cb, kAsLam + l, lam);
+    const uint64_t lm = __ballot(live);   // (by every lane, outside the branch)
+    if (l == 0) cb_st(as.cb, kAsLive, (int64_t)lm);
+    as_issue(as, kCmdBwd);
+    const TwFwd fw = tw_forward(S, D, L, n, lam, live, ck, steps);
+    if (!as_wait(P, as)) {
+        TwistOut o;
+        o.neg = 0; o.r = 0; o.gam = 0.0; o.nrm2 = 1.0; o.bad = 0; o.guarded = 0;
+        return o;
+    }
+    const double mwb = as_ldd(as.cb, kAsMw + l);
+    const bool bfin = cb_ld(as.cb, kAsFin + l) != 0;
+    // the helper ranks the upper blocks from gamma_{n-1} on, the leader the
+    // lower ones from scratch
+    const int64_t half = ((cl + 1) / 8) * 4;
+    as_std(as.cb, kAsBest + l, fabs(fw.wl) * __builtin_amdgcn_rcp(fabs(fw.vl)));   // gamma_{n-1} = d+_{n-1}
+    if (l == 0) cb_st(as.cb, kAsHalf, half);
+    as_issue(as, kCmdGamma);
+    double best = __builtin_inf();
+    int r = -1;
+    tw_gamma_blocks(S, D, L, n, lam, live, ck, 0, half - 1, best, r, steps);
+    if (!as_wait(P, as)) {
+        TwistOut o;
+        o.neg = 0; o.r = 0; o.gam = 0.0; o.nrm2 = 1.0; o.bad = 0; o.guarded = 0;
+        return o;
+    }
+    const double best_h = as_ldd(as.cb, kAsBest + l);
+    const int r_h = (int)cb_ld(as.cb, kAsRb + l);
+    if (!(r >= 0 && best <= best_h)) r = r_h;
+    return tw_at_r(D, L, n, lam, live, ck, r, fw, bfin, fmin(fw.mw, mwb));
+}
+
+// The helper's side: join the bundle whose block is at `off`, then answer
+// its commands until the leader is finished.
+DEV void task_assist(Shared& S, const Params& P, int64_t off, int64_t& steps) {
+    const int l = lane_id();
+    int64_t* cb = reinterpret_cast<int64_t*>(P.arena + off);
+    int joined = 0;
+    if (l == 0) {
+        int64_t expect = 0;
+        joined = __hip_atomic_compare_exchange_strong(cb + kAsJoin, &expect, (int64_t)1, __ATOMIC_ACQ_REL,
+                                                      __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ? 1 : 0;
+    }
+    if (!__shfl(joined, 0)) return;
+    const int node_id = (int)cb_ld(cb, kAsNode);
+    const Node nd = P.nodes[node_id];
+    const Block blk = P.blocks[nd.block];
+    const int64_t n = blk.n;
+    const double* D = P.arena + nd.data;
+    const double* L = D + n;
+    const int64_t stride = cb_ld(cb, kAsStride);
+    const int64_t cl = (n - 1) / kCkb;
+    const uint64_t t0 = wall_clock64();
+    int64_t last = 0;
+    for (;;) {
+        int64_t gen = 0;
+        if (l == 0) {
+            for (;;) {
+                gen = __hip_atomic_load(cb + kAsGen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (gen != last) break;
+                if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    wall_clock64() - t0 > P.timeout_ticks) {
+                    gen = kAsDone;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        gen = __shfl(gen, 0);
+        if (gen == kAsDone) return;
+        last = gen;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int cmd = (int)(gen & 0xff);
+        const bool live = ((uint64_t)cb_ld(cb, kAsLive) >> l) & 1ull;
+        const double lam = as_ldd(cb, kAsLam + l);
+        CkPtr ck;
+        ck.base = P.ck + cb_ld(cb, kAsCk + l);
+        ck.stride = stride;
+        if (cmd == kCmdBwd) {
+            bool fin = true;
+            const double mw = tw_backward_plain(S, D, L, n, lam, live, ck, fin, steps);
+            as_std(cb, kAsMw + l, mw);
+            cb_st(cb, kAsFin + l, fin ? 1 : 0);
+        } else if (cmd == kCmdGamma) {
+            double best = as_ldd(cb, kAsBest + l);
+            int r = (int)(n - 1);
+            tw_gamma_blocks(S, D, L, n, lam, live, ck, cb_ld(cb, kAsHalf), cl, best, r, steps);
+            as_std(cb, kAsBest + l, best);
+            cb_st(cb, kAsRb + l, r);
+        } else if (cmd == kCmdVecUp) {
+            const int r = (int)cb_ld(cb, kAsR + l);
+            const double scale = as_ldd(cb, kAsScale + l);
+            double* zcol = P.Z + cb_ld(cb, kAsZ + l);
+            const double ss = solve_vector_hom(S, D, L, n, lam, live, r, scale, ck, zcol, true, 1, steps);
+            as_std(cb, kAsMw + l, ss);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (l == 0) __hip_atomic_store(cb + kAsAck, gen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// twisted() with the helper: the shared transforms, then the guarded form for
+// the lanes that need it, on the leader alone.
+DEV TwistOut twisted_assisted(Shared& S, const Params& P, const double* D, const double* L, int64_t n, double lam,
+                              bool live, const CkPtr& ck, Assist& as, int64_t& steps) {
+    TwistOut o = twisted_split(S, P, D, L, n, lam, live, ck, as, steps);
+    const bool redo = live && o.bad;
+    if (wave_or(redo ? 1 : 0)) {
+        const TwistOut g = twisted_impl<true>(S, D, L, n, lam, redo, ck, steps);
+        if (lane_id() == 0) S.redo += 1;
+        if (redo) {
+            o = g;
+            o.guarded = 1;
+        }
+    }
+    return o;
+}
+
+// solve_vector() with the helper: it writes the rows below the twist, the
+// leader the rest; a NaN in either part, or a guarded lane, goes to the
+// guarded form on the leader alone.
+DEV void solve_vector_assisted(Shared& S, const Params& P, const double* D, const double* L, int64_t n, double lam,
+                               bool live, int r, double scale, const CkPtr& ck, double* zcol, bool guarded,
+                               Assist& as, int64_t& steps) {
+    const int l = lane_id();
+    const bool hl = live && !guarded;
+    as_std(as.cb, kAsLam + l, lam);
+    cb_st(as.cb, kAsR + l, r);
+    as_std(as.cb, kAsScale + l, scale);
+    cb_st(as.cb, kAsZ + l, (int64_t)(zcol - P.Z));
+    const uint64_t lm = __ballot(hl);   // (by every lane, outside the branch)
+    if (l == 0) cb_st(as.cb, kAsLive, (int64_t)lm);
+    as_issue(as, kCmdVecUp);
+    const double ss = solve_vector_hom(S, D, L, n, lam, hl, r, scale, ck, zcol, true, 2, steps);
+    if (!as_wait(P, as)) return;
+    const double ssh = as_ldd(as.cb, kAsMw + l);
+    const bool redo = live && (guarded || __builtin_isnan(ss) || __builtin_isnan(ssh));
+    if (wave_or(redo ? 1 : 0)) {
+        solve_vector_impl<true>(S, D, L, n, lam, redo, r, scale, ck, zcol, true, steps);
+        if (lane_id() == 0) S.redo += 1;
+    }
+}
+
 // A bundle of singletons of one node, one per lane (Alg. 4.3): Rayleigh
 // quotient iteration on twisted factorisations with the inertia of Delta_r
 // guarding the direction; bisection to full accuracy plus one more Getvec as
@@ -3044,6 +3498,12 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
     CkPtr ck;
     ck.base = P.ck + pr.ck_base + (blk.col0 + (j - blk.w0));   // one column per output column
     ck.stride = pr.ck_stride;
+    // a helper for long representations when a worker is idle
+    Assist as;
+    as.cb = nullptr;
+    as.gen = 0;
+    as.on = false;
+    const int64_t ck_off = (int64_t)(ck.base - P.ck);
     // tol1: the local residual may stop at n eps gap in FP64; with data in a
     // coarser format (unit roundoff eps_x) the orthogonality goal is
     // eps_x sqrt(n), and the iteration stops at eps_x sqrt(n) gap (Sec. 5.1.1)
@@ -3094,7 +3554,9 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
             __syncthreads();
             continue;
         }
-        const TwistOut tw = twisted(S, D, L, n, lam, live, ck, steps);
+        assist_try(P, as, node_id, n, pr.ck_stride, ck_off);
+        const TwistOut tw = as.on ? twisted_assisted(S, P, D, L, n, lam, live, ck, as, steps)
+                                  : twisted(S, D, L, n, lam, live, ck, steps);
         nrqi += __popcll(__ballot(live));
         if (live) {
             const bool below = tw.neg >= j;       // lambda_j < lam
@@ -3121,6 +3583,7 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
         }
     }
     if (__ballot(act && !done) != 0ull) {
+        assist_close(as);
         set_error(P, kErrNoConv);
         return;
     }
@@ -3134,7 +3597,9 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
             if (!fin) nrm2 = ss;
         }
         const double scale = 1.0 / sqrt(nrm2);
-        solve_vector(S, D, L, n, lam, act, r, scale, ck, zcol, true, tg, steps);
+        assist_try(P, as, node_id, n, pr.ck_stride, ck_off);
+        if (as.on) solve_vector_assisted(S, P, D, L, n, lam, act, r, scale, ck, zcol, tg, as, steps);
+        else solve_vector(S, D, L, n, lam, act, r, scale, ck, zcol, true, tg, steps);
         if (pr.flags & 1) {
             // several blocks: the rest of each column is zero, written column
             // by column with the wave's lanes on consecutive rows
@@ -3150,6 +3615,7 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
         }
     }
     if (act) P.w[pr.woff + col] = (nd.sigma + lam) * pr.tscale_inv;
+    assist_close(as);
     add_stat(&P.ctl->n_rqi, nrqi);
     add_stat(&P.ctl->n_fallback, nfb);
 }
@@ -3216,6 +3682,10 @@ extern "C" __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1
                     case kTaskSingle: task_single(S, P, tk.node, tk.a, tk.b, steps); ++nsingle; break;
                     case kTaskHelp:
                         task_help(S, P, (int64_t)((uint64_t)(uint32_t)tk.a | ((uint64_t)(uint32_t)tk.b << 32)), steps);
+                        break;
+                    case kTaskAssist:
+                        task_assist(S, P, (int64_t)((uint64_t)(uint32_t)tk.a | ((uint64_t)(uint32_t)tk.b << 32)),
+                                    steps);
                         break;
                     default: set_error(P, kErrInternal); break;
                 }
