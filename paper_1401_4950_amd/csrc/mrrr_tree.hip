@@ -3578,6 +3578,25 @@ DEV void task_single(Shared& S, const Params& P, int node_id, int off, int cnt, 
                     prev = fabs(rqc);
                 } else {
                     need_fb = true;
+                    // The bisection starts next to lam, which the count has
+                    // just confirmed as one end.  The other end is put at four
+                    // times the rejected correction (a correction that stopped
+                    // shrinking still measures the distance), or, when its
+                    // sign was wrong, at twice the last accepted one; it is
+                    // checked by a count before the bracket can converge, and
+                    // moved outward if the check fails.  Without such a scale
+                    // the bracket stays as it is.
+                    double w2 = __builtin_inf();
+                    if (fin && sign_ok && cand >= lo && cand <= hi) w2 = 4.0 * fabs(rqc);
+                    else if (fin) w2 = 2.0 * prev;
+                    w2 = fmax(w2, 8.0 * kEps * fabs(lam));
+                    if (below) {
+                        const double e2 = lam - w2;
+                        if (e2 > lo) { lo = e2; vf &= ~1; }
+                    } else {
+                        const double e2 = lam + w2;
+                        if (e2 < hi) { hi = e2; vf &= ~2; }
+                    }
                 }
             }
         }
