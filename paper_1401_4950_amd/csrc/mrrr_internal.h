@@ -95,6 +95,11 @@ struct Node {
     double spdiam;    // spectral diameter of the block's root
     double checked;   // nonzero: the columns of this node or of an ancestor
                       // are checked for orthogonality after the tree
+    double share;     // workers its refinement slices may occupy: at a root the
+                      // block's share of the launch, at a child its parent's
+                      // share times its part of the parent's clustered members
+    int32_t clustered;  // members in clusters, written by its classification
+    int32_t pad;
 };
 
 // Columns of a cluster whose representation passed no element-growth test

@@ -1681,10 +1681,9 @@ DEV int slice_q(const int* mb, double Pb, const double* bpp, const int* cf, int 
 // The members' needs are in P.need (written with their brackets, see
 // member_bits); maxbits is the largest.  Eight pass budgets are counted in one
 // sweep over the members.
-DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int mode, int64_t block_rows, int smax,
+DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int mode, double share, int smax,
                      int64_t sb, int lanes, int maxbits) {
     const int l = lane_id();
-    const double share = (double)P.nworkers * (double)block_rows / (double)(P.total_rows > 0 ? P.total_rows : 1);
     const int budget = share < 1.0 ? 1 : (int)share;
     int qmin = 0, qmax = 0;
     while ((1 << (qmin + 1)) <= P.slice_min && qmin < 6) ++qmin;
@@ -2427,11 +2426,12 @@ DEV void classify(Shared& S, const Params& P, int node_id) {
     const int64_t sb = blk.row0 - 1;
     const int a = nd.a, b = nd.b;
     const bool depth_cap = (nd.depth + 1 >= P.max_depth);
-    // pass 1: count singletons
-    int nsing = 0;
+    // pass 1: count singletons, and the members in clusters (whose tasks
+    // divide this node's share of the workers among them)
+    int nsing = 0, nclu = 0;
     for (int base = a; base <= b; base += kWave) {
         const int j = base + l;
-        bool single = false;
+        bool single = false, clu = false;
         if (j <= b) {
             const double lo = ld_rlx_d(P.lo + sb + j), hi = ld_rlx_d(P.hi + sb + j);
             bool sbf = (j == a), saf = (j == b);
@@ -2439,9 +2439,13 @@ DEV void classify(Shared& S, const Params& P, int node_id) {
             if (!saf) saf = pair_split(lo, hi, ld_rlx_d(P.lo + sb + j + 1), ld_rlx_d(P.hi + sb + j + 1), P.gaptol);
             if (depth_cap) sbf = saf = true;
             single = sbf && saf && j >= blk.w0 && j <= blk.w1;
+            clu = !(sbf && saf);
         }
         nsing += __popcll(__ballot(single));
+        nclu += __popcll(__ballot(clu));
     }
+    // read by the cluster tasks (published by their push)
+    if (l == 0) P.nodes[node_id].clustered = nclu;
     int64_t off = 0;
     if (l == 0 && nsing > 0)
         off = __hip_atomic_fetch_add(&P.ctl->slist_top, (int64_t)nsing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2660,6 +2664,8 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     }
     const int id = new_node(P);
     if (id < 0) return;
+    // the block's share of the launch's workers (its part of all rows)
+    const double root_share = (double)P.nworkers * (double)n / (double)(P.total_rows > 0 ? P.total_rows : 1);
     if (l == 0) {
         Node nd;
         nd.data = off;
@@ -2674,6 +2680,9 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         nd.rgap = __builtin_inf();
         nd.spdiam = spdiam;
         nd.checked = 0.0;
+        nd.share = root_share;
+        nd.clustered = 0;
+        nd.pad = 0;
         P.nodes[id] = nd;
         P.blocks[bid].root = id;
     }
@@ -2717,7 +2726,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
         S.info_d[1] = spdiam;
     }
     add_stat(&P.ctl->n_nodes, 1);
-    push_slices(S, P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, blk.n,
+    push_slices(S, P, id, (int)blk.k0, (int)blk.k1, P.jobz ? kModeClass : kModeFull, root_share,
                 P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes, maxbits);
 }
 
@@ -2784,6 +2793,14 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     const Block blk = P.blocks[par.block];
     const int64_t n = blk.n;
     const double* D = P.arena + par.data;
+    // the child's share of the workers: twice its part of the parent's
+    // clustered members, at most the parent's share.  Clusters of one parent
+    // refine side by side; a share of exactly their part left workers idle
+    // while they waited for each other's slower levels (glued Wilkinson), the
+    // parent's whole share for each made their slices queue behind each
+    // other's (1.3x the time)
+    const double frac = (double)(q - p + 1) / (double)(par.clustered > 0 ? par.clustered : 1);
+    const double child_share = fmin(par.share, 2.0 * par.share * frac);
     const double* L = D + n;
     const int64_t sb = blk.row0 - 1;
     // the new representation's D+ and L+, then the selection's checkpoints
@@ -3002,6 +3019,9 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
         nd.rgap = rgap;
         nd.spdiam = spd;
         nd.checked = checked;
+        nd.share = child_share;
+        nd.clustered = 0;
+        nd.pad = 0;
         P.nodes[id] = nd;
     }
     // 3. child brackets: (lambda(1 -+ nu) - tau)(1 -+ nu), nu = 10 k_rr n eps
@@ -3054,7 +3074,8 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     if (l == 0) {
         __hip_atomic_fetch_max(&P.ctl->dmax, par.depth + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    push_slices(S, P, id, p, q, kModeClass, n, P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes, maxbits);
+    push_slices(S, P, id, p, q, kModeClass, child_share, P.probs[blk.prob].slice_max, sb, P.probs[blk.prob].lanes,
+                maxbits);
 }
 
 // ------------------------------------- a helper for a singleton bundle
