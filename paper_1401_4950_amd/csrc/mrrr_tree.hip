@@ -1842,11 +1842,25 @@ DEV int coop_lg(int nu, int lanes) {   // refine_members' points per member for 
     return Lg;
 }
 
+// What the counts run on: a node's representation (D, L), or, for the
+// extremal eigenvalues of a root, the block's T itself (d non-null), whose
+// multisection points are equally spaced.
+struct CoopSrc {
+    const double* D;
+    const double* L;
+    const double* d;
+    const double* e;
+    double sc;
+};
+DEV double coop_point(bool onT, double lo, double hi, int t, int Lg) {
+    return onT ? lo + (hi - lo) * (double)(t + 1) / (double)(Lg + 1) : msec_point(lo, hi, t, Lg);
+}
+
 // A helper's share of a round: branch g = (rank - 1) * (64 / Lg) + l / Lg is
 // bracket b of the a-th unfinished member; lane k of the branch counts point
 // k of the next pass inside that bracket.
-DEV void coop_branches(Shared& S, int64_t* cb, const double* D, const double* L, int64_t n, int rank,
-                       uint64_t act, int Lg, int64_t& steps) {
+DEV void coop_branches(Shared& S, int64_t* cb, const CoopSrc& src, int64_t n, int rank, uint64_t act, int Lg,
+                       int64_t& steps) {
     const int l = lane_id();
     const int nu = __popcll(act);
     if ((act >> l) & 1ull) S.ulist[__popcll(act & ((1ull << l) - 1ull))] = l;
@@ -1859,10 +1873,11 @@ DEV void coop_branches(Shared& S, int64_t* cb, const double* D, const double* L,
     const double lo = __longlong_as_double((long long)cb_ld(cb, kCbLo + m));
     const double hi = __longlong_as_double((long long)cb_ld(cb, kCbHi + m));
     const int j = (int)cb_ld(cb, kCbJ + m);
-    const double lob = (b == 0) ? lo : msec_point(lo, hi, b - 1, Lg);
-    const double hib = (b == Lg) ? hi : msec_point(lo, hi, b, Lg);
-    const double sig = on ? msec_point(lob, hib, k, Lg) : 0.0;
-    const int c = negcount_rep(S, D, L, n, sig);
+    const bool onT = src.d != nullptr;
+    const double lob = (b == 0) ? lo : coop_point(onT, lo, hi, b - 1, Lg);
+    const double hib = (b == Lg) ? hi : coop_point(onT, lo, hi, b, Lg);
+    const double sig = on ? coop_point(onT, lob, hib, k, Lg) : 0.0;
+    const int c = onT ? negcount_T(S, src.d, src.e, n, src.sc, sig) : negcount_rep(S, src.D, src.L, n, sig);
     steps += n * (int64_t)__popcll(__ballot(on));
     const int gb = (l / Lg) * Lg;
     const uint64_t gmask = (Lg == 64) ? ~0ull : (((1ull << Lg) - 1ull) << (gb & 63));
@@ -1882,12 +1897,27 @@ DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
         rank = 1 + __hip_atomic_fetch_add(cb + kCbJoined, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     rank = __shfl(rank, 0);
     if (rank == 0) return;
+    // a node's representation, or (a negative word: -1 - block) a root's T
     const int pid = (int)cb_ld(cb, kCbNode);
-    const Node nd = P.nodes[pid];
-    const Block blk = P.blocks[nd.block];
-    const int64_t n = blk.n;
-    const double* D = P.arena + nd.data;
-    const double* L = D + n;
+    CoopSrc src;
+    int64_t n;
+    if (pid >= 0) {
+        const Node nd = P.nodes[pid];
+        n = P.blocks[nd.block].n;
+        src.D = P.arena + nd.data;
+        src.L = src.D + n;
+        src.d = nullptr;
+        src.e = nullptr;
+        src.sc = 1.0;
+    } else {
+        const Block blk = P.blocks[-1 - pid];
+        n = blk.n;
+        src.D = nullptr;
+        src.L = nullptr;
+        src.d = P.d + blk.row0;
+        src.e = P.e + blk.row0;
+        src.sc = P.probs[blk.prob].tscale;
+    }
     const uint64_t t0 = wall_clock64();
     int64_t last = 0;
     for (;;) {
@@ -1911,7 +1941,7 @@ DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
         if (rank >= M) continue;   // joined after this round was laid out
         const uint64_t act = (uint64_t)cb_ld(cb, kCbAct);
         const int Lg = (int)cb_ld(cb, kCbLg);
-        coop_branches(S, cb, D, L, n, (int)rank, act, Lg, steps);
+        coop_branches(S, cb, src, n, (int)rank, act, Lg, steps);
         // the results out (every lane's stores are complete), then the arrival
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (l == 0) __hip_atomic_fetch_add(cb + kCbArrive, (int64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -2065,6 +2095,120 @@ DEV int coop_helpers(const Params& P) {
     const int64_t idle = (int64_t)P.nworkers - pend;
     const int h = (int)(idle / 4 < kCoopMax - 1 ? idle / 4 : kCoopMax - 1);
     return h >= 3 ? h : 0;
+}
+
+// The extremal eigenvalues of a long block's T with idle workers' help.  The
+// root's own schedule (each pass 32 equally spaced points inside each of the
+// two brackets, both ends every pass until both are delta wide) advances two
+// passes a round as in coop_refine: the leader counts the first, helpers the
+// second inside every bracket the first can leave an end in.  The brackets
+// are those of the sequential passes, bit for bit, with any number of
+// helpers.  False on an error or a time-out; the brackets are then valid for
+// the sequential passes to continue.
+constexpr int kRootCoopHelpers = 33;   // 2 ends x 33 brackets, 2 branches a helper
+DEV bool root_extremal_coop(Shared& S, const Params& P, int bid, const double* d, const double* e, int64_t n,
+                            double sc, double delta, double& lo1, double& hi1, double& lon, double& hin, int64_t* cb,
+                            int64_t cboff, int helpers, int64_t& steps) {
+    const int l = lane_id();
+    constexpr int Lg = 32;
+    if (l == 0) {
+        cb_st(cb, kCbGen, 0);
+        cb_st(cb, kCbJoined, 0);
+        cb_st(cb, kCbArrive, 0);
+        cb_st(cb, kCbNode, -1 - bid);
+        cb_st(cb, kCbJ + 0, 1);
+        cb_st(cb, kCbJ + 1, n);
+    }
+    if (!push_batch(P, kQRefine, helpers, [&](int) {
+            Task t;
+            t.type = kTaskHelp;
+            t.node = 0;
+            t.a = (int32_t)(uint32_t)((uint64_t)cboff & 0xffffffffull);
+            t.b = (int32_t)(uint32_t)((uint64_t)cboff >> 32);
+            return t;
+        }))
+        return false;
+    const uint64_t tw = wall_clock64();
+    int64_t joined = 0;
+    if (l == 0) {
+        for (;;) {
+            joined = cb_ld(cb, kCbJoined);
+            if (joined >= helpers || wall_clock64() - tw > 4000) break;   // 40 us of the 100 MHz clock
+            __builtin_amdgcn_s_sleep(8);
+        }
+    }
+    bool ok = true;
+    const int half = l >> 5, t = l & 31;
+    for (int round = 1; round < 200; ++round) {
+        if (hi1 - lo1 <= delta && hin - lon <= delta) break;
+        if (l == 0) joined = cb_ld(cb, kCbJoined);
+        joined = __shfl(joined, 0);
+        const int M = 1 + (int)(joined < helpers ? joined : helpers);
+        if (l == 0) {
+            cb_st(cb, kCbLo + 0, __double_as_longlong(lo1));
+            cb_st(cb, kCbHi + 0, __double_as_longlong(hi1));
+            cb_st(cb, kCbLo + 1, __double_as_longlong(lon));
+            cb_st(cb, kCbHi + 1, __double_as_longlong(hin));
+            cb_st(cb, kCbArrive, 0);
+            cb_st(cb, kCbAct, 3);
+            cb_st(cb, kCbLg, Lg);
+        }
+        for (int g = l; g < 2 * (Lg + 1); g += kWave) cb_st(cb, kCbRes + g, 0);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (l == 0) __hip_atomic_store(cb + kCbGen, ((int64_t)round << 8) | M, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        // the first pass, as the sequential loop counts it
+        const double lo = half ? lon : lo1, hi = half ? hin : hi1;
+        const double sig = coop_point(true, lo, hi, t, Lg);
+        const int c = negcount_T(S, d, e, n, sc, sig);
+        steps += n * kWave;
+        const uint64_t ge = __ballot(c >= (half ? (int)n : 1));
+        const uint64_t g0 = ge & 0xffffffffull, g1 = ge >> 32;
+        const int t0 = g0 ? __ffsll((unsigned long long)g0) - 1 : 32;
+        const int t1 = g1 ? __ffsll((unsigned long long)g1) - 1 : 32;
+        const double h0 = __shfl(sig, t0 < 32 ? t0 : 31), l0 = __shfl(sig, t0 > 0 ? t0 - 1 : 0);
+        const double h1 = __shfl(sig, 32 + (t1 < 32 ? t1 : 31)), l1 = __shfl(sig, 32 + (t1 > 0 ? t1 - 1 : 0));
+        int stop = 0;
+        if (l == 0) {
+            const uint64_t t2 = wall_clock64();
+            while (__hip_atomic_load(cb + kCbArrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < M - 1) {
+                if (__hip_atomic_load(&P.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    wall_clock64() - t2 > P.timeout_ticks) {
+                    stop = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        // the first pass's brackets (kept even when the round stops here)
+        if (t0 < 32) hi1 = h0;
+        if (t0 > 0) lo1 = l0;
+        if (t1 < 32) hin = h1;
+        if (t1 > 0) lon = l1;
+        if (__shfl(stop, 0)) {
+            ok = false;
+            break;
+        }
+        // the second pass, where both outcomes were counted and the
+        // sequential loop would run it (not both ends delta wide yet)
+        const int64_t r0 = cb_ld(cb, kCbRes + t0), r1 = cb_ld(cb, kCbRes + (Lg + 1) + t1);
+        if (r0 != 0 && r1 != 0 && !(hi1 - lo1 <= delta && hin - lon <= delta)) {
+            const int u0 = (int)r0 - 1, u1 = (int)r1 - 1;
+            const double a0 = (u0 > 0) ? coop_point(true, lo1, hi1, u0 - 1, Lg) : lo1;
+            const double b0 = (u0 < Lg) ? coop_point(true, lo1, hi1, u0, Lg) : hi1;
+            const double a1 = (u1 > 0) ? coop_point(true, lon, hin, u1 - 1, Lg) : lon;
+            const double b1 = (u1 < Lg) ? coop_point(true, lon, hin, u1, Lg) : hin;
+            lo1 = a0;
+            hi1 = b0;
+            lon = a1;
+            hin = b1;
+        }
+        __syncthreads();
+    }
+    if (l == 0) __hip_atomic_store(cb + kCbGen, kCbDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return ok;
 }
 
 DEV int64_t arena_alloc(const Params& P, int64_t count) {
@@ -2372,8 +2516,13 @@ DEV FacOut factor_select(Shared& S, const double* d, const double* e, int64_t n,
     return o;
 }
 
+// The rows of the chosen root factorization, each tile from its checkpoint
+// (lanes run tiles side by side); what is stored is each datum times its
+// pseudo-random relative perturbation 1 + amp u (Alg. 3.2; u from the seed
+// and the global row g: 2g for d, 2g + 1 for l), while the recurrence goes on
+// with the unperturbed value.
 DEV void factor_values(const double* d, const double* e, int64_t n, double sc, double mu, const double* ckp, int c,
-                       double* Dd, double* Ld) {
+                       double* Dd, double* Ld, uint64_t seed, double amp, int64_t row0) {
     const int l = lane_id();
     const int64_t ntiles = (n + kTile - 1) / kTile;
     for (int64_t tile = l; tile < ntiles; tile += kWave) {
@@ -2397,10 +2546,12 @@ DEV void factor_values(const double* d, const double* e, int64_t n, double sc, d
                         dv = dd[k] - mu;
                     } else {
                         const double lv = quot(recip(dprev), ee[k]);
-                        Ld[i - 1] = lv;
+                        const uint64_t gl = (uint64_t)(row0 + i - 1);
+                        Ld[i - 1] = lv * (1.0 + amp * unit_pm1(seed, 2 * gl + 1));
                         dv = (dd[k] - mu) - lv * ee[k];
                     }
-                    Dd[i] = dv;
+                    const uint64_t g = (uint64_t)(row0 + i);
+                    Dd[i] = dv * (1.0 + amp * unit_pm1(seed, 2 * g));
                     dprev = dv;
                 }
             }
@@ -2585,11 +2736,23 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     // lanes 32-63 lambda_n, until the brackets are 4 n eps bnorm wide
     double delta = 4.0 * (double)n * kEps * fmax(bnorm, kSafmin);
     double lo1 = gl, hi1 = gu, lon = gl, hin = gu;
+    // the root's representation, the selection's checkpoints and (at
+    // 4n + 128) the block of the cooperative passes
+    const int64_t off = arena_alloc(P, 4 * n + kNodeExtra);
+    if (off < 0) return;
+    if (n >= kCoopMinRows) {
+        // long blocks: with idle workers' help (the same brackets either way)
+        const int h = coop_helpers(P);
+        if (h > 0)
+            root_extremal_coop(S, P, bid, d, e, n, sc, delta, lo1, hi1, lon, hin,
+                               reinterpret_cast<int64_t*>(P.arena + off + 4 * n + 128), off + 4 * n + 128,
+                               h < kRootCoopHelpers ? h : kRootCoopHelpers, steps);
+    }
     const int half = l >> 5, t = l & 31;
     for (int pass = 0; pass < 200; ++pass) {
         if (hi1 - lo1 <= delta && hin - lon <= delta) break;
         const double lo = half ? lon : lo1, hi = half ? hin : hi1;
-        const double sig = lo + (hi - lo) * (double)(t + 1) / 33.0;
+        const double sig = coop_point(true, lo, hi, t, 32);
         const int c = negcount_T(S, d, e, n, sc, sig);
         steps += n * kWave;
         const uint64_t ge = __ballot(c >= (half ? (int)n : 1));
@@ -2605,8 +2768,6 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     }
     // root shift mu: just outside either end, so that T - mu I is definite
     // (lane 0 the left candidate, lane 1 the right one)
-    const int64_t off = arena_alloc(P, 4 * n + kNodeExtra);
-    if (off < 0) return;
     double* C0 = P.arena + off;
     double* ckp = P.arena + off + 2 * n;   // the selection's checkpoints
     double mul = lo1 - delta, mur = hin + delta;
@@ -2632,18 +2793,11 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     }
     const double mu = side ? mur : mul;
     __syncthreads();
-    factor_values(d, e, n, sc, mu, ckp, side, C0, C0 + n);
-    __syncthreads();   // the rows other lanes wrote are read below
+    // the rows, each datum perturbed by a pseudo-random relative amount of at
+    // most xi*eps (Alg. 3.2)
+    factor_values(d, e, n, sc, mu, ckp, side, C0, C0 + n, P.seed, P.xi * kEps, blk.row0);
     double* Dr = C0;
     double* Lr = Dr + n;
-    // pseudo-random relative perturbation of every datum by at most xi*eps
-    // (Alg. 3.2)
-    const double amp = P.xi * kEps;
-    for (int64_t i = l; i < n; i += kWave) {
-        const uint64_t g = (uint64_t)(blk.row0 + i);
-        Dr[i] = Dr[i] * (1.0 + amp * unit_pm1(P.seed, 2 * g));
-        if (i < n - 1) Lr[i] = Lr[i] * (1.0 + amp * unit_pm1(P.seed, 2 * g + 1));
-    }
     // this wave reads the perturbed rows next; other workers get them through
     // the release of the pushes below
     __threadfence_block();
