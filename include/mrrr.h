@@ -105,7 +105,13 @@ typedef struct {
                                 twisted factorisations and eigenvector solve
                                 (the results are the same bit for bit);
                                 0: never */
-    int32_t pad2;
+    int32_t pass_helpers;    /* 1 (default): on a representation of 4096 rows
+                                or more, idle workers, when there are any, count
+                                multisection points for the refinement of a
+                                cluster's end eigenvalues and of the root's
+                                extremal eigenvalues (Sec. 4.1.3 R-tasks; the
+                                brackets, and so the results, are the same bit
+                                for bit); 0: never */
 } mrrr_options_t;
 
 /* One record per executed device task (the per-task timeline of the

@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
         ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int64),
         ("lanes_per_eig", ctypes.c_int32), ("bundle", ctypes.c_int32),
         ("tune", ctypes.c_void_p), ("check_tol", ctypes.c_double), ("cond_growth_k", ctypes.c_double),
-        ("bundle_helpers", ctypes.c_int32), ("pad2", ctypes.c_int32),
+        ("bundle_helpers", ctypes.c_int32), ("pass_helpers", ctypes.c_int32),
     ]
 
 

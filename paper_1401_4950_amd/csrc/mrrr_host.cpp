@@ -145,7 +145,7 @@ extern "C" void mrrr_default_options(mrrr_options_t* o) {
     o->check_tol = 20.0;
     o->cond_growth_k = 10.0;
     o->bundle_helpers = 1;
-    o->pad2 = 0;
+    o->pass_helpers = 1;
 }
 
 extern "C" const char* mrrr_status_string(int s) {
@@ -309,6 +309,7 @@ void set_options(Params& P, const mrrr_options_t& o, double wall_khz, int worker
     P.slice_min = std::max(1, o.slice_min);
     P.sign_conv = o.sign_convention;
     P.assist = o.bundle_helpers != 0 ? 1 : 0;
+    P.coop = o.pass_helpers != 0 ? 1 : 0;
     P.nworkers = workers;
     P.timeout_ticks = (uint64_t)std::max(1.0, o.timeout_s * wall_khz * 1000.0);
     P.trace = (o.trace && o.trace_cap > 0) ? static_cast<TraceRec*>(o.trace) : nullptr;

@@ -215,6 +215,7 @@ struct Params {
     uint64_t seed;
     int32_t max_rqi, max_tries, max_depth, slice_min, sign_conv;
     int32_t assist;       // singleton bundles may take a helper (same results)
+    int32_t coop;         // idle workers may share refinement passes (same results)
     uint64_t timeout_ticks;
     TraceRec* trace;
     int64_t trace_cap;

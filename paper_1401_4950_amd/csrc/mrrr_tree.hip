@@ -2740,7 +2740,7 @@ DEV void task_root(Shared& S, const Params& P, int bid, int64_t& steps) {
     // 4n + 128) the block of the cooperative passes
     const int64_t off = arena_alloc(P, 4 * n + kNodeExtra);
     if (off < 0) return;
-    if (n >= kCoopMinRows) {
+    if (n >= kCoopMinRows && P.coop) {
         // long blocks: with idle workers' help (the same brackets either way)
         const int h = coop_helpers(P);
         if (h > 0)
@@ -2987,7 +2987,7 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     // long representations: with idle workers' help when there are any (the
     // brackets are those of the sequential schedule either way)
     bool ends_done = false;
-    if (n >= kCoopMinRows && (S.m_flag[0] & 3) == 3 && (S.m_flag[1] & 3) == 3 &&
+    if (n >= kCoopMinRows && P.coop && (S.m_flag[0] & 3) == 3 && (S.m_flag[1] & 3) == 3 &&
         !(bracket_done(P, C.mode, S.m_lo[0], S.m_hi[0]) && bracket_done(P, C.mode, S.m_lo[1], S.m_hi[1]))) {
         const int helpers = coop_helpers(P);
         if (helpers > 0)

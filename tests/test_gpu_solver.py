@@ -278,6 +278,31 @@ def test_bundle_helpers_change_nothing(fam, n):
     assert torch.equal(w0, w1) and torch.equal(Z0, Z1)
 
 
+@pytest.mark.parametrize("fam,n", [("121", 8000), ("random", 12000), ("glued_wilkinson", 8400)])
+def test_pass_helpers_change_nothing(fam, n):
+    """Idle workers count the second multisection pass of each round of the
+    root's extremal eigenvalues and of the cluster ends' refinement (helper
+    tasks of type 5 in the trace); the brackets are those of the sequential
+    passes, so the result must equal, bit for bit, that of a solve with the
+    helpers switched off."""
+    import torch
+    import paper_1401_4950_amd as mr
+    from paper_1401_4950_amd import _lib
+    d, e = ti.family(fam, n, 0)
+    cap = 400000
+    buf = torch.zeros(cap * _lib.TRACE_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    w1, Z1 = mr.eigh_tridiagonal(to_dev(d), to_dev(e), options={"trace": buf.data_ptr(), "trace_cap": cap})
+    torch.cuda.synchronize()
+    st = mr.last_stats()
+    rec = np.frombuffer(buf.cpu().numpy().tobytes(), dtype=np.dtype(_lib.TRACE_FIELDS))[: min(st["n_tasks"], cap)]
+    n_help = int((rec["type"] == 5).sum())
+    w0, Z0 = mr.eigh_tridiagonal(to_dev(d), to_dev(e), options={"pass_helpers": 0})
+    torch.cuda.synchronize()
+    print(f"{fam} n={n}: {n_help} pass helpers")
+    assert n_help > 0
+    assert torch.equal(w0, w1) and torch.equal(Z0, Z1)
+
+
 @pytest.mark.parametrize("fam,n", [("glued_wilkinson", 4200), ("clement", 6000)])
 def test_shared_end_refinement_families(orc, fam, n):
     """Long representations (helpers join the cluster ends' refinement):
