@@ -23,7 +23,7 @@ constexpr int kNumQ = 3;       // 0: refine, 1: root + cluster, 2: singleton
 // node pool doubles per representation of an n-row block: 4 n + kNodeExtra
 // (D and L; the shift selection's two checkpoint arrays of n + 64; the block
 // of the cooperative end refinement)
-constexpr int64_t kNodeExtra = 512;
+constexpr int64_t kNodeExtra = 1024;
 constexpr int kQRefine = 0, kQCluster = 1, kQSingle = 2;
 
 enum TaskType : int32_t {

@@ -1814,6 +1814,14 @@ DEV int new_node(const Params& P) {   // all lanes get the id
 // next round or, finding the refinement finished, returns at once.
 constexpr int kCoopMax = 66;                // workers per round, the leader included
 constexpr int64_t kCoopMinRows = 4096;      // shorter passes are not worth sharing
+// The three-pass rounds of a cluster whose children have most of the workers
+// (a chain of representations, as in 1-2-1): both ends refined with 16
+// points each and pass, every member on its own (Lg fixed); helpers count the
+// second pass inside each of the 17 brackets the first can leave a member in,
+// and the third inside each of the 17 x 17 the first two can.
+constexpr int kDeepLg = 16;
+constexpr double kDeepShare = 256.0;        // a child's share of the workers from which the ends go deep
+constexpr int kCoopMaxDeep = 1 + (2 * (kDeepLg + 1) * (kDeepLg + 2) + kWave / kDeepLg - 1) / (kWave / kDeepLg);
 enum CoopWord : int {
     kCbGen = 0,     // (round << 8) | M while a round runs; -1 once finished
     kCbJoined,      // helpers that have joined (their ranks are 1, 2, ...)
@@ -1821,14 +1829,19 @@ enum CoopWord : int {
     kCbNode,        // the node whose representation is refined
     kCbAct,         // bit m: member m unfinished (64-bit mask)
     kCbLg,          // points per member in this round's passes
+    kCbLv,          // passes a round can advance (2, or 3 for the deep rounds)
     kCbLo = 8,      // [64] the round's brackets
     kCbHi = kCbLo + kWave,
     kCbJ = kCbHi + kWave,          // [64] the members' indices
-    kCbRes = kCbJ + kWave,         // [128] per (member, bracket): 1 + first point reaching j; 0 not counted
-    kCbWords = kCbRes + 2 * kWave
+    // per second-pass branch (member, bracket), then per third-pass branch
+    // (member, bracket, bracket): 1 + first point reaching j; 0 not counted
+    kCbRes = kCbJ + kWave,
+    kCbWords = kCbRes + 2 * (kDeepLg + 1) * (kDeepLg + 2)
 };
 constexpr int64_t kCbDone = -1;
 static_assert(128 + kCbWords <= kNodeExtra, "a representation's node-pool share holds the cooperation block");
+static_assert(2 * (32 + 1) <= 2 * (kDeepLg + 1) * (kDeepLg + 2), "the result words hold the two-pass rounds too");
+static_assert(kCoopMaxDeep <= 255, "the round word holds the workers of a round");
 
 DEV int64_t cb_ld(int64_t* cb, int w) {
     return __hip_atomic_load(cb + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1856,26 +1869,43 @@ DEV double coop_point(bool onT, double lo, double hi, int t, int Lg) {
     return onT ? lo + (hi - lo) * (double)(t + 1) / (double)(Lg + 1) : msec_point(lo, hi, t, Lg);
 }
 
-// A helper's share of a round: branch g = (rank - 1) * (64 / Lg) + l / Lg is
-// bracket b of the a-th unfinished member; lane k of the branch counts point
-// k of the next pass inside that bracket.
+// A helper's share of a round: branch g = (rank - 1) * (64 / Lg) + l / Lg.
+// The first nu (Lg + 1) branches are (a, b): bracket b of the a-th
+// unfinished member after the first pass; in rounds of three passes the next
+// nu (Lg + 1)^2 are (a, b, c): bracket c inside that one after the second.
+// Lane k of the branch counts point k of the next pass inside its bracket.
 DEV void coop_branches(Shared& S, int64_t* cb, const CoopSrc& src, int64_t n, int rank, uint64_t act, int Lg,
-                       int64_t& steps) {
+                       int lv, int64_t& steps) {
     const int l = lane_id();
     const int nu = __popcll(act);
     if ((act >> l) & 1ull) S.ulist[__popcll(act & ((1ull << l) - 1ull))] = l;
     __syncthreads();
-    const int bp = kWave / Lg, nbr = nu * (Lg + 1);
+    const int bp = kWave / Lg, w1 = Lg + 1, nbr2 = nu * w1, nbr = nbr2 + (lv >= 3 ? nu * w1 * w1 : 0);
     const int g = (rank - 1) * bp + l / Lg, k = l % Lg;
     const bool on = g < nbr;
-    const int a = on ? g / (Lg + 1) : 0, b = on ? g % (Lg + 1) : 0;
+    int a = 0, b = 0, c3 = -1;
+    if (on && g < nbr2) {
+        a = g / w1;
+        b = g % w1;
+    } else if (on) {
+        const int h = g - nbr2;
+        a = h / (w1 * w1);
+        b = (h / w1) % w1;
+        c3 = h % w1;
+    }
     const int m = S.ulist[a];
     const double lo = __longlong_as_double((long long)cb_ld(cb, kCbLo + m));
     const double hi = __longlong_as_double((long long)cb_ld(cb, kCbHi + m));
     const int j = (int)cb_ld(cb, kCbJ + m);
     const bool onT = src.d != nullptr;
-    const double lob = (b == 0) ? lo : coop_point(onT, lo, hi, b - 1, Lg);
-    const double hib = (b == Lg) ? hi : coop_point(onT, lo, hi, b, Lg);
+    double lob = (b == 0) ? lo : coop_point(onT, lo, hi, b - 1, Lg);
+    double hib = (b == Lg) ? hi : coop_point(onT, lo, hi, b, Lg);
+    if (c3 >= 0) {
+        const double l2 = (c3 == 0) ? lob : coop_point(onT, lob, hib, c3 - 1, Lg);
+        const double h2 = (c3 == Lg) ? hib : coop_point(onT, lob, hib, c3, Lg);
+        lob = l2;
+        hib = h2;
+    }
     const double sig = on ? coop_point(onT, lob, hib, k, Lg) : 0.0;
     const int c = onT ? negcount_T(S, src.d, src.e, n, src.sc, sig) : negcount_rep(S, src.D, src.L, n, sig);
     steps += n * (int64_t)__popcll(__ballot(on));
@@ -1941,7 +1971,8 @@ DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
         if (rank >= M) continue;   // joined after this round was laid out
         const uint64_t act = (uint64_t)cb_ld(cb, kCbAct);
         const int Lg = (int)cb_ld(cb, kCbLg);
-        coop_branches(S, cb, src, n, (int)rank, act, Lg, steps);
+        const int lv = (int)cb_ld(cb, kCbLv);
+        coop_branches(S, cb, src, n, (int)rank, act, Lg, lv, steps);
         // the results out (every lane's stores are complete), then the arrival
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         if (l == 0) __hip_atomic_fetch_add(cb + kCbArrive, (int64_t)1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1954,8 +1985,12 @@ DEV void task_help(Shared& S, const Params& P, int64_t cboff, int64_t& steps) {
 // brackets share one interval (refine_members then starts with a joint
 // pass) or on an error; the brackets are then valid for refine_members to
 // finish.  `publish` writes the final brackets to the members' slots.
+// `lg_fix` > 0: the deep schedule -- every unfinished member gets lg_fix
+// points per pass whatever the others do, so each advances on its own, up to
+// three passes a round.
 DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const double* L, int64_t n, int nm,
-                     int mode, int lanes, int64_t* cb, int64_t cboff, int helpers, bool publish, int64_t& steps) {
+                     int mode, int lanes, int64_t* cb, int64_t cboff, int helpers, bool publish, int lg_fix,
+                     int64_t& steps) {
     const int l = lane_id();
     {
         int same = 1;
@@ -1996,8 +2031,9 @@ DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const
         const uint64_t act = __ballot(l < nm && !bracket_done(P, mode, lo, hi));
         if (act == 0ull) break;
         const int nu = __popcll(act);
-        const int Lg = coop_lg(nu, lanes);
-        const int nbr = nu * (Lg + 1);
+        const int Lg = lg_fix > 0 ? lg_fix : coop_lg(nu, lanes);
+        const int lv = lg_fix > 0 ? 3 : 2;
+        const int nbr = nu * (Lg + 1) + (lv >= 3 ? nu * (Lg + 1) * (Lg + 1) : 0);
         if (l == 0) joined = cb_ld(cb, kCbJoined);
         joined = __shfl(joined, 0);
         const int M = 1 + (int)(joined < helpers ? joined : helpers);
@@ -2010,6 +2046,7 @@ DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const
             cb_st(cb, kCbArrive, 0);
             cb_st(cb, kCbAct, (int64_t)act);
             cb_st(cb, kCbLg, Lg);
+            cb_st(cb, kCbLv, lv);
         }
         // every lane's stores out before the round is published
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -2063,13 +2100,34 @@ DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const
         const bool fin1 = lead && bracket_done(P, mode, nlo, nhi);
         int64_t res = 0;
         if (lead) res = cb_ld(cb, kCbRes + u * (Lg + 1) + tstar);
-        const bool two = __ballot(fin1) == 0ull && __ballot(lead && res == 0) == 0ull;
-        if (lead && two) {
+        if (lg_fix == 0) {
+            const bool two = __ballot(fin1) == 0ull && __ballot(lead && res == 0) == 0ull;
+            if (lead && two) {
+                const int t2 = (int)res - 1;
+                const double a2 = (t2 > 0) ? msec_point(nlo, nhi, t2 - 1, Lg) : nlo;
+                const double b2 = (t2 < Lg) ? msec_point(nlo, nhi, t2, Lg) : nhi;
+                nlo = a2;
+                nhi = b2;
+            }
+        } else if (lead && !fin1 && res != 0) {
+            // the deep schedule: the second pass where it was counted, and
+            // the third where the member is still unfinished and it was too
             const int t2 = (int)res - 1;
             const double a2 = (t2 > 0) ? msec_point(nlo, nhi, t2 - 1, Lg) : nlo;
             const double b2 = (t2 < Lg) ? msec_point(nlo, nhi, t2, Lg) : nhi;
             nlo = a2;
             nhi = b2;
+            if (!bracket_done(P, mode, nlo, nhi)) {
+                const int64_t r3 =
+                    cb_ld(cb, kCbRes + nu * (Lg + 1) + (u * (Lg + 1) + tstar) * (Lg + 1) + t2);
+                if (r3 != 0) {
+                    const int t3 = (int)r3 - 1;
+                    const double a3 = (t3 > 0) ? msec_point(nlo, nhi, t3 - 1, Lg) : nlo;
+                    const double b3 = (t3 < Lg) ? msec_point(nlo, nhi, t3, Lg) : nhi;
+                    nlo = a3;
+                    nhi = b3;
+                }
+            }
         }
         __syncthreads();
         if (lead) {
@@ -2088,12 +2146,12 @@ DEV bool coop_refine(Shared& S, const Params& P, int pid, const double* D, const
 
 // Helpers from workers that are idle now: tasks pushed and not yet finished
 // occupy (or wait for) the others.  0 when too few are idle to be worth it.
-DEV int coop_helpers(const Params& P) {
+DEV int coop_helpers(const Params& P, int cap = kCoopMax) {
     int64_t pend = 0;
     if (lane_id() == 0) pend = __hip_atomic_load(&P.ctl->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     pend = __shfl(pend, 0);
     const int64_t idle = (int64_t)P.nworkers - pend;
-    const int h = (int)(idle / 4 < kCoopMax - 1 ? idle / 4 : kCoopMax - 1);
+    const int h = (int)(idle / 4 < cap - 1 ? idle / 4 : cap - 1);
     return h >= 3 ? h : 0;
 }
 
@@ -2152,6 +2210,7 @@ DEV bool root_extremal_coop(Shared& S, const Params& P, int bid, const double* d
             cb_st(cb, kCbArrive, 0);
             cb_st(cb, kCbAct, 3);
             cb_st(cb, kCbLg, Lg);
+            cb_st(cb, kCbLv, 2);
         }
         for (int g = l; g < 2 * (Lg + 1); g += kWave) cb_st(cb, kCbRes + g, 0);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -2986,13 +3045,22 @@ DEV void task_cluster(Shared& S, const Params& P, int pid, int p, int q, int64_t
     C.lanes = P.probs[blk.prob].lanes;
     // long representations: with idle workers' help when there are any (the
     // brackets are those of the sequential schedule either way)
+    // A cluster whose child gets most of the workers (a chain of
+    // representations) takes the deep schedule, with or without helpers.
     bool ends_done = false;
-    if (n >= kCoopMinRows && P.coop && (S.m_flag[0] & 3) == 3 && (S.m_flag[1] & 3) == 3 &&
+    const bool deep = n >= kCoopMinRows && child_share >= kDeepShare && C.lanes >= kDeepLg;
+    if (n >= kCoopMinRows && (S.m_flag[0] & 3) == 3 && (S.m_flag[1] & 3) == 3 &&
         !(bracket_done(P, C.mode, S.m_lo[0], S.m_hi[0]) && bracket_done(P, C.mode, S.m_lo[1], S.m_hi[1]))) {
-        const int helpers = coop_helpers(P);
-        if (helpers > 0)
+        if (deep) {
             ends_done = coop_refine(S, P, pid, D, L, n, 2, C.mode, C.lanes,
-                                    reinterpret_cast<int64_t*>(P.arena + cboff), cboff, helpers, true, steps);
+                                    reinterpret_cast<int64_t*>(P.arena + cboff), cboff,
+                                    P.coop ? coop_helpers(P, kCoopMaxDeep) : 0, true, kDeepLg, steps);
+        } else if (P.coop) {
+            const int helpers = coop_helpers(P);
+            if (helpers > 0)
+                ends_done = coop_refine(S, P, pid, D, L, n, 2, C.mode, C.lanes,
+                                        reinterpret_cast<int64_t*>(P.arena + cboff), cboff, helpers, true, 0, steps);
+        }
     }
     if (!ends_done) refine_members(S, P, D, L, n, 2, C, steps);
     const double lo_p = S.m_lo[0], hi_p = S.m_hi[0];
