@@ -1664,15 +1664,23 @@ DEV void chunk_maxbits(int bits, int* mb) {
         mb[q + 1] = m;
     }
 }
-DEV int slice_q(const int* mb, double Pb, const double* bpp, const int* cf, int qmin, int qmax) {
-    // bpp[k] and cf[k] are for slices of 64 >> k members, i.e. q = 6 - k;
-    // cf passes confirm the members' unverified bracket ends first.  The
-    // largest fitting q in (qmin, qmax], else qmin; every block size is
+// The most bits a member of an aligned block of 2^k members can still get
+// within the pass budget Pb, cap[k] = floor((Pb - cf) * bpp) for k = 1..6
+// (bpp[i] and cf[i] are for slices of 64 >> i members, i.e. q = 6 - i; cf
+// passes confirm the members' unverified bracket ends first).  An integer
+// need fits exactly when it is at most cap[k].
+DEV void slice_caps(double Pb, const double* bpp, const int* cf, int* cap) {
+    cap[0] = 0;
+#pragma unroll
+    for (int k = 1; k <= 6; ++k) cap[k] = (int)floor((Pb - (double)cf[6 - k]) * bpp[6 - k]);
+}
+DEV int slice_q(const int* mb, const int* cap, int qmin, int qmax) {
+    // the largest fitting q in (qmin, qmax], else qmin; every block size is
     // tested (constant indices keep the arrays in registers)
     int q = qmin;
 #pragma unroll
     for (int k = 1; k <= 6; ++k) {
-        const bool fit = (double)mb[k] <= (Pb - (double)cf[6 - k]) * bpp[6 - k];
+        const bool fit = mb[k] <= cap[k];
         q = (k > qmin && k <= qmax && fit) ? k : q;
     }
     return q;
@@ -1703,10 +1711,12 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
     constexpr int kAheadChunks = 4;   // chunks whose needs are loaded together
     int Pb = 0, ns = 0;
     for (int round = 0; round < 4 && Pb == 0; ++round) {
-        int pbk[kTry], nsk[kTry];
+        int pbk[kTry], nsk[kTry], capk[kTry][7];
+#pragma unroll
         for (int t = 0; t < kTry; ++t) {
             pbk[t] = P0 + (P0 * t) / 4 + t;
             nsk[t] = 0;
+            slice_caps((double)pbk[t], bpp, cf, capk[t]);
         }
         for (int base = a; base <= b; base += kAheadChunks * kWave) {
             int nd[kAheadChunks];
@@ -1723,7 +1733,7 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
                 chunk_maxbits(nd[k], mb);
 #pragma unroll
                 for (int t = 0; t < kTry; ++t) {
-                    const int q = slice_q(mb, (double)pbk[t], bpp, cf, qmin, qmax);
+                    const int q = slice_q(mb, capk[t], qmin, qmax);
                     nsk[t] += __popcll(__ballot(in && (l & ((1 << q) - 1)) == 0));
                 }
             }
@@ -1739,6 +1749,8 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
     if (l == 0) __hip_atomic_store(&P.nodes[node_id].pending, ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // list the slices in LDS and push the list whenever it fills (one wait
     // for free cells per 64 slices instead of one per 64-member chunk)
+    int capf[7];
+    slice_caps((double)Pb, bpp, cf, capf);
     int listed = 0;
     int nd[kAheadChunks];
     for (int base = a; base <= b; base += kWave) {
@@ -1757,7 +1769,7 @@ DEV void push_slices(Shared& S, const Params& P, int node_id, int a, int b, int 
 #pragma unroll
         for (int u = 1; u < kAheadChunks; ++u) ndk = (kc == u) ? nd[u] : ndk;
         chunk_maxbits(ndk, mb);
-        const int q = slice_q(mb, (double)Pb, bpp, cf, qmin, qmax);
+        const int q = slice_q(mb, capf, qmin, qmax);
         const bool st = in && (l & ((1 << q) - 1)) == 0;
         const uint64_t sm = __ballot(st);
         if (st) {
